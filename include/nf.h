@@ -1,0 +1,197 @@
+/*
+ * nf.h -- C ABI of libnf.so: the two-vector Four-Russians fill of the Nussinov
+ * base-pair maximisation table on one AMD MI355X (gfx950) GPU.
+ *
+ * Problem (Section 2, Eq. 1): for S_1..S_n over {A,C,G,U},
+ *     D(i,i-1) = D(i,i) = 0,
+ *     D(i,j) = max{ b(S_i,S_j) + D(i+1,j-1), max_{i+1<=k<=j} D(i,k-1) + D(k,j) },
+ * b = 1 for A-U, U-A, C-G, G-C and 0 otherwise (G-U is not a pair, there is no
+ * minimum hairpin loop).  The score is D(1,n).
+ *
+ * Method (Section 3.1, Eq. 2 -> Eq. 3, Lemma 1, and the tiled parallel form
+ * of Sections 4-5): rows and columns of the table are cut into groups of q
+ * split points; q consecutive table cells are a base value plus a 0/1
+ * difference vector, and the best of q splits is the two bases plus one
+ * lookup R[v][v-bar] into a table built once per q.  Tiles are swept as an
+ * anti-diagonal wavefront.  The table the GPU returns is identical to Eq. 1's.
+ *
+ * General conventions
+ *  - Every function returns NF_OK (0) or a negative NF_E_* code (nf_fold also
+ *    returns the score >= 0).  On error nothing is written to the outputs and
+ *    nf_last_error() describes the failure (thread-local string, valid until
+ *    the next call on that thread).
+ *  - Sequences: n bytes of 'A','C','G','U' (lower case accepted); any other
+ *    byte (including 'T' and 'N') is NF_E_INVAL.  0 <= n <= NF_MAX_N.
+ *  - q: 1..8, or 0 to let the library choose (autotuned value, else 8).
+ *  - Table layout (S_out, row-major n*n int16, caller-owned):
+ *        S_out[i*n + j] = D(i+1, j+1) for i <= j, and 0 for i > j.
+ *  - Inputs are borrowed for the duration of the call (nf_submit copies);
+ *    outputs are caller-allocated.  Device memory the library needs is
+ *    allocated and owned by the library and released by nf_shutdown().
+ *  - Host functions are thread-safe; calls are serialised internally.
+ *  - No GPU fallback: without a usable gfx950 device every call that needs
+ *    the GPU returns NF_E_DEVICE.
+ */
+#ifndef NF_H
+#define NF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    NF_OK = 0,
+    NF_E_INVAL = -1,     /* bad argument or bad base */
+    NF_E_NOMEM = -2,     /* device memory exhausted, or request above the serving budget */
+    NF_E_DEVICE = -3,    /* no GPU, HIP error, or wrong architecture */
+    NF_E_BUSY = -4,      /* serving queue full */
+    NF_E_NOTFOUND = -5,  /* unknown or already released ticket */
+    NF_E_TOOLONG = -6,   /* n > NF_MAX_N */
+    NF_E_TIMEOUT = -7,   /* nf_wait deadline passed */
+    NF_E_ABORTED = -8    /* serving engine shut down before the request finished */
+};
+
+/* Scores are at most n/2 and are stored in int16 tables. */
+#define NF_MAX_N 65534
+#define NF_Q_MIN 1
+#define NF_Q_MAX 8
+
+/* Message for the last negative return on the calling thread ("" if none). */
+const char* nf_last_error(void);
+
+/* Select and initialise the GPU (default device 0; the environment variable
+ * NF_DEVICE overrides).  Idempotent; called implicitly by every GPU entry
+ * point.  NF_E_DEVICE when no gfx950 device is present. */
+int nf_init(int device);
+
+/* Release every device buffer, cached plan and graph, and stop the serving
+ * engine (pending tickets then report NF_E_ABORTED).  The library can be used
+ * again afterwards. */
+void nf_shutdown(void);
+
+/* ---- Four-Russians table R (Section 3.1, preprocessing listing; Eq. 3) ----
+ * Builds R for vectors of length q on the device, once per q (cached;
+ * idempotent).  Encoding: v_0 = v-bar_0 = 0 carry no information, so
+ * h has bit p-1 = v_p and c has bit p-1 = -v-bar_p for p = 1..q-1, and
+ *     R[h][c] = max_{k=0..q-1} sum_{p<=k} (v_p + v-bar_p)   (values 0..q-1).
+ * Stored as uint8, row-major [2^(q-1)][2^(q-1)]. */
+int nf_precompute_R(int q);
+
+/* Copy R for q (building it if needed) into out: 2^(2(q-1)) bytes, row h,
+ * column c.  NF_E_INVAL if cap is smaller. */
+int nf_copy_R(int q, uint8_t* out, size_t cap);
+
+/* ---- Single fold (host buffers) ----
+ * Fold seq[0..n) and return D(1,n) >= 0.  If S_out is not NULL, the full table
+ * (layout above) is written to it.  Synchronous. */
+int nf_fold(const char* seq, int n, int q, int16_t* S_out);
+
+/* ---- Single fold (device buffers, asynchronous on a HIP stream) ----
+ * d_codes: n device bytes, base codes A=0, C=1, G=2, U=3 (other values give
+ *          unspecified scores but never access memory out of bounds).
+ * d_score: device int32 that receives D(1,n) (may be NULL).
+ * d_S:     device int16 n*n table, layout above (may be NULL; when set the
+ *          lower triangle is written as 0).
+ * stream:  hipStream_t passed as void* (NULL = the null stream).
+ * Work is enqueued on stream and the call returns without waiting.  The
+ * library keeps a per-(n,q) workspace; concurrent calls with the same (n,q)
+ * on different streams must be ordered by the caller. */
+int nf_fold_dev(const uint8_t* d_codes, int n, int q, int32_t* d_score, int16_t* d_S, void* stream);
+
+/* ---- Batched folds: one packed wavefront over many sequences ----
+ * A prepared batch uploads the codes of all sequences once, builds the packed
+ * per-diagonal work lists and captures the whole fill as one HIP graph.
+ * Handles are opaque; a handle must only be used from one thread at a time. */
+typedef struct nf_batch nf_batch;
+
+/* seqs[i] holds ns[i] bases (i < count).  q as above (0 = autotuned for the
+ * batch's longest sequence). */
+int nf_batch_create(const char* const* seqs, const int* ns, int count, int q, nf_batch** out);
+/* Enqueue one complete fill of every sequence in the batch on stream. */
+int nf_batch_run(nf_batch* b, void* stream);
+/* Wait for the last run and copy the count scores to host memory. */
+int nf_batch_scores(nf_batch* b, int32_t* scores_out);
+/* Wait for the last run and copy the table of sequence idx (ns[idx]^2 int16). */
+int nf_batch_table(nf_batch* b, int idx, int16_t* S_out);
+/* Number of sequences and total device bytes the batch holds. */
+int nf_batch_info(const nf_batch* b, int* count, size_t* device_bytes);
+void nf_batch_destroy(nf_batch* b);
+
+/* Convenience: create, run, copy scores (and the tables for every non-NULL
+ * S_outs[i] when S_outs is not NULL), destroy.  Synchronous. */
+int nf_fold_batch(const char* const* seqs, const int* ns, int count, int q,
+                  int32_t* scores_out, int16_t* const* S_outs);
+
+/* ---- Serving: continuous batching ----
+ * A background engine keeps admitted folds resident on the device and
+ * advances every active fold by one tile diagonal per device step; requests
+ * that arrive while others run join at the next step when a slot and enough
+ * of the device-memory budget are free. */
+
+/* Configure before the first nf_submit (or after nf_shutdown):
+ * hbm_budget_bytes = device bytes the active folds may hold together
+ * (0 = 80% of free device memory); max_slots = folds active at once (0 = 256);
+ * max_queue = pending requests before NF_E_BUSY (0 = 65536). */
+int nf_serve_config(size_t hbm_budget_bytes, int max_slots, int max_queue);
+
+/* Device bytes a fold of length n would hold while active under q. */
+size_t nf_fold_bytes(int n, int q);
+
+/* Queue a fold (the sequence is copied).  Returns a ticket >= 0 or a negative
+ * code: NF_E_INVAL/NF_E_TOOLONG for bad input, NF_E_NOMEM if the fold alone is
+ * larger than the budget, NF_E_BUSY if the queue is full.  Never waits on the
+ * GPU.  want_table != 0 keeps the full table for nf_poll. */
+int64_t nf_submit(const char* seq, int n, int q, int want_table);
+
+/* 1 = done (outputs written, ticket released), 0 = still pending, < 0 error.
+ * score_out may be NULL; S_out (n*n int16) may be NULL, and is ignored unless
+ * the ticket was submitted with want_table. */
+int nf_poll(int64_t ticket, int32_t* score_out, int16_t* S_out);
+
+/* Like nf_poll but blocks up to timeout_ms (< 0: no limit); NF_E_TIMEOUT when
+ * the deadline passes first (the ticket stays valid). */
+int nf_wait(int64_t ticket, int timeout_ms, int32_t* score_out, int16_t* S_out);
+
+/* Engine counters: admitted, completed, rejected requests, device steps run,
+ * and the largest number of budget bytes ever held by active folds. */
+typedef struct {
+    int64_t submitted, admitted, completed, rejected, steps;
+    int64_t active, pending;
+    size_t budget_bytes, peak_bytes;
+} nf_serve_stats_t;
+int nf_serve_stats(nf_serve_stats_t* out);
+
+/* ---- Tuning ----
+ * q and launch shape chosen for sequences of length n (what q = 0 resolves
+ * to).  The choice comes from the autotune cache file named by
+ * NF_AUTOTUNE_CACHE if set and readable, else from built-in defaults. */
+int nf_autotune_q(int n);
+/* Time the fill for q in qmin..qmax at length n (reps folds each) and record
+ * the fastest in the in-memory cache (and in the cache file if set).  Returns
+ * the chosen q. */
+int nf_autotune(int n, int qmin, int qmax, int reps);
+
+/* ---- Diagnostics ----
+ * Per-kernel timing of the fill of one sequence given as device codes (as in
+ * nf_fold_dev).  Runs the fill reps times with one launch per work list (no
+ * graph), each launch bracketed by HIP events recorded on stream, and sums per
+ * kernel class k: 0 = main-diagonal tiles, 1 = tile finish, 2 = between-group
+ * lookups.  lookups[k] counts the Four-Russians steps of Eq. 3 the launches
+ * performed on table cells (padding excluded); cells[k] the table cells they
+ * finished.  Synchronous. */
+typedef struct {
+    int64_t launches[3];
+    double ms[3];
+    double lookups[3];
+    double cells[3];
+    int q, tile, tiles_per_side, stages;
+} nf_kernel_profile_t;
+int nf_profile_fold(const uint8_t* d_codes, int n, int q, int reps, void* stream, nf_kernel_profile_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NF_H */

@@ -1,0 +1,348 @@
+// extern "C" entry points of include/nf.h.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "nf.h"
+#include "nf_runtime.h"
+
+using namespace nf;
+
+namespace {
+std::recursive_mutex g_api;
+}
+
+struct nf_batch {
+    std::unique_ptr<Plan> plan;
+    std::vector<int> ns;
+    hipEvent_t done = nullptr;
+    bool ran = false;
+    ~nf_batch()
+    {
+        if (done) (void)hipEventDestroy(done);
+    }
+};
+
+extern "C" {
+
+const char* nf_last_error(void) { return last_error(); }
+
+int nf_init(int device)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    Context& c = ctx();
+    if (!c.ready) c.requested_device = device;
+    return ensure_device();
+}
+
+void nf_shutdown(void)
+{
+    serve_shutdown();
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    Context& c = ctx();
+    if (!c.ready) return;
+    (void)hipSetDevice(c.device);
+    (void)hipDeviceSynchronize();
+    c.plans.clear();
+    for (auto& r : c.R) r.reset();
+    if (c.stream) (void)hipStreamDestroy(c.stream);
+    if (c.capture_stream) (void)hipStreamDestroy(c.capture_stream);
+    c.stream = c.capture_stream = nullptr;
+    c.ready = false;
+}
+
+int nf_precompute_R(int q)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (q < NF_Q_MIN || q > NF_Q_MAX) return fail(NF_E_INVAL, "q = %d outside %d..%d", q, NF_Q_MIN, NF_Q_MAX);
+    int rc = ensure_device();
+    if (rc) return rc;
+    const uint8_t* R = nullptr;
+    return get_R(q, &R);
+}
+
+int nf_copy_R(int q, uint8_t* out, size_t cap)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (q < NF_Q_MIN || q > NF_Q_MAX) return fail(NF_E_INVAL, "q = %d outside %d..%d", q, NF_Q_MIN, NF_Q_MAX);
+    const size_t bytes = (size_t)1 << (2 * (q - 1));
+    if (!out || cap < bytes) return fail(NF_E_INVAL, "R for q = %d needs %zu bytes", q, bytes);
+    int rc = ensure_device();
+    if (rc) return rc;
+    const uint8_t* R = nullptr;
+    if ((rc = get_R(q, &R))) return rc;
+    HIPCHK(hipMemcpy(out, R, bytes, hipMemcpyDeviceToHost));
+    return NF_OK;
+}
+
+int nf_fold(const char* seq, int n, int q, int16_t* S_out)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    int rc = check_length(n);
+    if (rc) return rc;
+    if ((rc = check_q(q))) return rc;
+    if (!seq && n > 0) return fail(NF_E_INVAL, "seq is NULL");
+    std::vector<uint8_t> codes(n);
+    if ((rc = encode_sequence(seq, n, codes.data()))) return rc;
+    if ((rc = ensure_device())) return rc;
+    q = resolve_q(q, n);
+    Plan* p = nullptr;
+    if ((rc = single_plan(n, q, &p))) return rc;
+    const Geom& g = p->geom[0];
+    std::vector<uint8_t> padded(g.codes_bytes, 0);
+    std::copy(codes.begin(), codes.end(), padded.begin());
+    hipStream_t s = ctx().stream;
+    HIPCHK(hipMemcpyAsync((void*)p->h_folds[0].codes, padded.data(), g.codes_bytes, hipMemcpyHostToDevice, s));
+    if ((rc = plan_enqueue(*p, s))) return rc;
+    int32_t score = 0;
+    HIPCHK(hipMemcpyAsync(&score, p->d_scores.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (S_out && n > 0) {
+        const size_t bytes = (size_t)n * n * sizeof(int16_t);
+        if (p->d_S.bytes < bytes && (rc = p->d_S.alloc(bytes))) return rc;
+        HIPCHK(launch_expand(p->h_folds[0].F, g.ld, n, (int16_t*)p->d_S.p, s));
+        HIPCHK(hipMemcpyAsync(S_out, p->d_S.p, bytes, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return score;
+}
+
+int nf_fold_dev(const uint8_t* d_codes, int n, int q, int32_t* d_score, int16_t* d_S, void* stream)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    int rc = check_length(n);
+    if (rc) return rc;
+    if ((rc = check_q(q))) return rc;
+    if (!d_codes && n > 0) return fail(NF_E_INVAL, "d_codes is NULL");
+    if ((rc = ensure_device())) return rc;
+    q = resolve_q(q, n);
+    Plan* p = nullptr;
+    if ((rc = single_plan(n, q, &p))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const Geom& g = p->geom[0];
+    HIPCHK(launch_copy_codes(d_codes, n, (uint8_t*)p->h_folds[0].codes, (int)g.codes_bytes, s));
+    if ((rc = plan_enqueue(*p, s))) return rc;
+    if (d_score) HIPCHK(hipMemcpyAsync(d_score, p->d_scores.p, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (d_S && n > 0) HIPCHK(launch_expand(p->h_folds[0].F, g.ld, n, d_S, s));
+    return NF_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+int nf_batch_create(const char* const* seqs, const int* ns, int count, int q, nf_batch** out)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (!out) return fail(NF_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 0 || (count > 0 && (!seqs || !ns))) return fail(NF_E_INVAL, "bad batch arguments");
+    int rc = check_q(q);
+    if (rc) return rc;
+    int nmax = 0;
+    for (int i = 0; i < count; ++i) {
+        if ((rc = check_length(ns[i]))) return fail(rc, "sequence %d: %s", i, last_error());
+        if (!seqs[i] && ns[i] > 0) return fail(NF_E_INVAL, "sequence %d is NULL", i);
+        nmax = std::max(nmax, ns[i]);
+    }
+    std::vector<std::vector<uint8_t>> codes(count);
+    for (int i = 0; i < count; ++i) {
+        codes[i].resize(ns[i]);
+        if ((rc = encode_sequence(seqs[i], ns[i], codes[i].data()))) return fail(rc, "sequence %d: %s", i, last_error());
+    }
+    if ((rc = ensure_device())) return rc;
+    q = resolve_q(q, nmax);
+    auto b = std::make_unique<nf_batch>();
+    b->ns.assign(ns, ns + count);
+    if ((rc = make_plan(b->ns, q, b->plan))) return rc;
+    Plan& p = *b->plan;
+    // zero-padded codes of every fold; the host buffers live until the copies finish
+    hipStream_t s = ctx().stream;
+    for (int i = 0; i < count; ++i) {
+        codes[i].resize(p.geom[i].codes_bytes, 0);
+        HIPCHK(hipMemcpyAsync((void*)p.h_folds[i].codes, codes[i].data(), codes[i].size(), hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+    *out = b.release();
+    return NF_OK;
+}
+
+int nf_batch_run(nf_batch* b, void* stream)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (!b) return fail(NF_E_INVAL, "batch is NULL");
+    int rc = ensure_device();
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = plan_enqueue(*b->plan, s))) return rc;
+    HIPCHK(hipEventRecord(b->done, s));
+    b->ran = true;
+    return NF_OK;
+}
+
+int nf_batch_scores(nf_batch* b, int32_t* scores_out)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (!b || !scores_out) return fail(NF_E_INVAL, "NULL argument");
+    if (!b->ran) return fail(NF_E_INVAL, "batch has not been run");
+    HIPCHK(hipEventSynchronize(b->done));
+    if (!b->ns.empty())
+        HIPCHK(hipMemcpy(scores_out, b->plan->d_scores.p, b->ns.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return NF_OK;
+}
+
+int nf_batch_table(nf_batch* b, int idx, int16_t* S_out)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (!b || !S_out) return fail(NF_E_INVAL, "NULL argument");
+    if (idx < 0 || idx >= (int)b->ns.size()) return fail(NF_E_INVAL, "index %d out of range", idx);
+    if (!b->ran) return fail(NF_E_INVAL, "batch has not been run");
+    HIPCHK(hipEventSynchronize(b->done));
+    const int n = b->ns[idx];
+    if (n == 0) return NF_OK;
+    const size_t bytes = (size_t)n * n * sizeof(int16_t);
+    Plan& p = *b->plan;
+    int rc;
+    if (p.d_S.bytes < bytes && (rc = p.d_S.alloc(bytes))) return rc;
+    hipStream_t s = ctx().stream;
+    HIPCHK(launch_expand(p.h_folds[idx].F, p.geom[idx].ld, n, (int16_t*)p.d_S.p, s));
+    HIPCHK(hipMemcpyAsync(S_out, p.d_S.p, bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return NF_OK;
+}
+
+int nf_batch_info(const nf_batch* b, int* count, size_t* device_bytes)
+{
+    clear_error();
+    if (!b) return fail(NF_E_INVAL, "batch is NULL");
+    if (count) *count = (int)b->ns.size();
+    if (device_bytes) *device_bytes = b->plan->device_bytes;
+    return NF_OK;
+}
+
+void nf_batch_destroy(nf_batch* b)
+{
+    if (!b) return;
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    if (b->ran) (void)hipEventSynchronize(b->done);
+    delete b;
+}
+
+int nf_fold_batch(const char* const* seqs, const int* ns, int count, int q, int32_t* scores_out,
+                  int16_t* const* S_outs)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (!scores_out && count > 0) return fail(NF_E_INVAL, "scores_out is NULL");
+    nf_batch* b = nullptr;
+    int rc = nf_batch_create(seqs, ns, count, q, &b);
+    if (rc) return rc;
+    std::unique_ptr<nf_batch> hold(b);
+    if ((rc = nf_batch_run(b, ctx().stream))) return rc;
+    if ((rc = nf_batch_scores(b, scores_out))) return rc;
+    if (S_outs)
+        for (int i = 0; i < count; ++i)
+            if (S_outs[i] && (rc = nf_batch_table(b, i, S_outs[i]))) return rc;
+    return NF_OK;
+}
+
+// ------------------------------------------------------------------ serving
+
+int nf_serve_config(size_t hbm_budget_bytes, int max_slots, int max_queue)
+{
+    clear_error();
+    return serve_config(hbm_budget_bytes, max_slots, max_queue);
+}
+
+size_t nf_fold_bytes(int n, int q)
+{
+    if (n < 0 || n > NF_MAX_N || q < 0 || q > NF_Q_MAX) return 0;
+    if (q == 0) {
+        std::lock_guard<std::recursive_mutex> lk(g_api);
+        q = resolve_q(0, n);
+    }
+    return make_geom(n, q).bytes;
+}
+
+int64_t nf_submit(const char* seq, int n, int q, int want_table)
+{
+    clear_error();
+    return serve_submit(seq, n, q, want_table);
+}
+
+int nf_poll(int64_t ticket, int32_t* score_out, int16_t* S_out)
+{
+    clear_error();
+    return serve_poll(ticket, score_out, S_out, 0, false);
+}
+
+int nf_wait(int64_t ticket, int timeout_ms, int32_t* score_out, int16_t* S_out)
+{
+    clear_error();
+    return serve_poll(ticket, score_out, S_out, timeout_ms, true);
+}
+
+int nf_serve_stats(nf_serve_stats_t* out)
+{
+    clear_error();
+    if (!out) return fail(NF_E_INVAL, "out is NULL");
+    return serve_stats(out);
+}
+
+// ------------------------------------------------------------------ tuning
+
+int nf_autotune_q(int n)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (n < 0 || n > NF_MAX_N) return fail(NF_E_INVAL, "length %d out of range", n);
+    return resolve_q(0, n);
+}
+
+int nf_autotune(int n, int qmin, int qmax, int reps)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    return autotune_run(n, qmin, qmax, reps);
+}
+
+int nf_profile_fold(const uint8_t* d_codes, int n, int q, int reps, void* stream, nf_kernel_profile_t* out)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (!out || reps < 1) return fail(NF_E_INVAL, "bad profile arguments");
+    int rc = check_length(n);
+    if (rc) return rc;
+    if ((rc = check_q(q))) return rc;
+    if (!d_codes && n > 0) return fail(NF_E_INVAL, "d_codes is NULL");
+    if ((rc = ensure_device())) return rc;
+    q = resolve_q(q, n);
+    Plan* p = nullptr;
+    if ((rc = single_plan(n, q, &p))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const Geom& g = p->geom[0];
+    HIPCHK(launch_copy_codes(d_codes, n, (uint8_t*)p->h_folds[0].codes, (int)g.codes_bytes, s));
+    memset(out, 0, sizeof *out);
+    out->q = q;
+    out->tile = tile_size(q);
+    out->tiles_per_side = g.NT;
+    out->stages = p->sc.stages;
+    return plan_profile(*p, s, reps, out);
+}
+
+}  // extern "C"
+
+namespace nf {
+// The serving engine takes the API lock for everything that touches the
+// shared context (plans, R tables).
+std::recursive_mutex& api_mutex() { return g_api; }
+}  // namespace nf

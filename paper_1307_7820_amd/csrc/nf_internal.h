@@ -1,0 +1,83 @@
+// Internal declarations shared by the kernels (nf_kernels.hip) and the host
+// runtime (nf_runtime.cpp).  Not part of the public ABI.
+//
+// Coordinates.  The kernels index the table of Eq. 1 by fence posts: post a
+// sits before base a+1, and F(a, b) = D(a+1, b) for 0 <= a <= b <= n.  Then
+// F(a, a) = F(a, a+1) = 0 and, for b >= a+2,
+//     F(a, b) = max{ b(S_{a+1}, S_b) + F(a+1, b-1), max_{a<m<b} F(a, m) + F(m, b) }.
+// The split point m = k-1 of Eq. 1 indexes both the row cell F(a, m) and the
+// column cell F(m, b), so the row grouping and the column grouping of
+// Section 3.1 (columns from 0, rows from 1, i.e. offset by one) become the
+// same grouping of posts: group K = posts [Kq, Kq+q-1].
+//
+// Tiles.  Posts 0..n are cut into NT tiles of T = G*q posts (G = 64/q groups,
+// T <= 64).  Tile (A, B), A <= B, holds F(a, b) for a in [AT, AT+T) and b in
+// [BT, BT+T); its diagonal is d = B - A.  Tiles are numbered diagonal-major:
+// tile_index(NT, A, d) = d*NT - d(d-1)/2 + A, so the tiles a wavefront step
+// writes are contiguous.
+//
+// Packed state of a finished off-diagonal tile (A, B) (Lemma 1: neighbours
+// differ by 0 or 1):
+//   row word (group k of the tile's columns, row i):
+//       bits 31..16 = F(a, BT+kq)               (base, Eq. 3 "D(i,l)")
+//       bits 15..0  = h << (q-1), bit p-1 of h = F(a, BT+kq+p) - F(a, BT+kq+p-1)
+//   column word (group k of the tile's rows, column j):
+//       bits 31..16 = F(AT+kq, b)               (base, Eq. 3 "D(l+1,j)")
+//       bits 15..0  = c, bit p-1 of c = F(AT+kq+p-1, b) - F(AT+kq+p, b)
+// Both are stored [k][64] per tile (64 words per group, rows/columns >= T
+// unused), so one group of one tile is one 256-byte line.  With these
+// encodings the Four-Russians step of Eq. 3 for cell (a, b) and group K is
+//     rowbase + colbase + R[(rw & 0xffff) + (cw & 0xffff)].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nf {
+
+constexpr int kThreads = 256;     // 4 wavefronts of 64 per workgroup
+constexpr int kRowsPerWave = 16;  // rows of a 64x64 tile held by one wavefront
+constexpr int kTileCells = 64 * 64;
+
+__host__ __device__ constexpr int groups_per_tile(int q) { return 64 / q; }
+__host__ __device__ constexpr int tile_size(int q) { return (64 / q) * q; }
+__host__ __device__ constexpr int state_words(int q) { return (64 / q) * 64; }
+__host__ __device__ inline long long tile_index(int NT, int A, int d)
+{
+    return (long long)d * NT - (long long)d * (d - 1) / 2 + A;
+}
+__host__ __device__ inline long long tile_count(int NT) { return (long long)NT * (NT + 1) / 2; }
+
+// One sequence being folded.  All pointers are device pointers.
+struct FoldDesc {
+    const uint8_t* codes;  // NT*T + 64 bytes: base codes A0 C1 G2 U3, zero padding
+    int16_t* F;            // ld x ld table of F(a, b), ld = NT*T
+    uint32_t* RS;          // row words, tile_count(NT) * state_words(q)
+    uint32_t* CS;          // column words, same size
+    int n, NT, ld, pad;
+};
+
+// Between-group work: tile (A, A+d) of fold `fold`, split groups of the
+// tiles C in [c0, c1) (A < c0 <= C < c1 <= A+d), result = one 64x64 int32
+// partial maximum written to partial slot `slot`.
+struct BetweenItem {
+    int fold, A, d, c0, c1, slot, pad0, pad1;
+};
+
+// Tile finish: tile (A, A+d) of fold `fold`; when nslot > 0 the partial
+// maxima in slots [slot0, slot0+nslot) are folded in first.
+struct TileItem {
+    int fold, A, d, slot0, nslot, pad0, pad1, pad2;
+};
+
+hipError_t launch_precompute_R(int q, uint8_t* R, hipStream_t s);
+hipError_t launch_copy_codes(const uint8_t* src, int n, uint8_t* dst, int padded, hipStream_t s);
+hipError_t launch_diag(int q, const FoldDesc* folds, const TileItem* items, int nitems, hipStream_t s);
+hipError_t launch_tile(int q, const FoldDesc* folds, const TileItem* items, int nitems,
+                       const uint8_t* R, const int32_t* part, hipStream_t s);
+hipError_t launch_between(int q, const FoldDesc* folds, const BetweenItem* items, int nitems,
+                          const uint8_t* R, int32_t* part, hipStream_t s);
+hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s);
+hipError_t launch_expand(const int16_t* F, int ld, int n, int16_t* S, hipStream_t s);
+
+}  // namespace nf

@@ -1,0 +1,614 @@
+// Host runtime behind the C ABI of include/nf.h: device context, R cache,
+// fold plans (workspace + packed wavefront schedule + captured HIP graph),
+// prepared batches, the serving engine and the q autotuner.
+#include "nf.h"
+#include "nf_internal.h"
+#include "nf_runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace nf {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+const char* last_error() { return g_err.c_str(); }
+void clear_error() { g_err.clear(); }
+
+// ------------------------------------------------------------------ device memory
+
+DevBuf::~DevBuf() { reset(); }
+void DevBuf::reset()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+int DevBuf::alloc(size_t nbytes)
+{
+    reset();
+    if (nbytes == 0) return NF_OK;
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        return fail(NF_E_NOMEM, "hipMalloc(%zu bytes): %s", nbytes, hipGetErrorString(e));
+    }
+    bytes = nbytes;
+    return NF_OK;
+}
+
+// ------------------------------------------------------------------ encoding
+
+int encode_sequence(const char* seq, int n, uint8_t* out)
+{
+    for (int i = 0; i < n; ++i) {
+        switch (seq[i]) {
+        case 'A': case 'a': out[i] = 0; break;
+        case 'C': case 'c': out[i] = 1; break;
+        case 'G': case 'g': out[i] = 2; break;
+        case 'U': case 'u': out[i] = 3; break;
+        default:
+            return fail(NF_E_INVAL, "base %d is 0x%02x, not one of A, C, G, U", i, (unsigned char)seq[i]);
+        }
+    }
+    return NF_OK;
+}
+
+int check_length(int n)
+{
+    if (n < 0) return fail(NF_E_INVAL, "negative length %d", n);
+    if (n > NF_MAX_N) return fail(NF_E_TOOLONG, "length %d exceeds NF_MAX_N (%d)", n, NF_MAX_N);
+    return NF_OK;
+}
+
+// ------------------------------------------------------------------ context
+
+Context& ctx()
+{
+    static Context c;
+    return c;
+}
+
+int ensure_device()
+{
+    Context& c = ctx();
+    if (c.ready) {
+        HIPCHK(hipSetDevice(c.device));
+        return NF_OK;
+    }
+    int dev = c.requested_device;
+    if (const char* env = getenv("NF_DEVICE")) dev = atoi(env);
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return fail(NF_E_DEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+    }
+    if (dev < 0 || dev >= count) return fail(NF_E_DEVICE, "device %d out of range (count %d)", dev, count);
+    HIPCHK(hipSetDevice(dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(NF_E_DEVICE, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+    c.device = dev;
+    c.num_cu = prop.multiProcessorCount;
+    HIPCHK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&c.capture_stream, hipStreamNonBlocking));
+    c.ready = true;
+    return NF_OK;
+}
+
+int get_R(int q, const uint8_t** out)
+{
+    Context& c = ctx();
+    if (q < NF_Q_MIN || q > NF_Q_MAX) return fail(NF_E_INVAL, "q = %d outside %d..%d", q, NF_Q_MIN, NF_Q_MAX);
+    DevBuf& b = c.R[q];
+    if (!b.p) {
+        const size_t bytes = (size_t)1 << (2 * (q - 1));
+        int rc = b.alloc(bytes < 16 ? 16 : bytes);
+        if (rc) return rc;
+        HIPCHK(launch_precompute_R(q, (uint8_t*)b.p, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+    }
+    *out = (const uint8_t*)b.p;
+    return NF_OK;
+}
+
+// ------------------------------------------------------------------ geometry & schedule
+
+Geom make_geom(int n, int q)
+{
+    Geom g;
+    const int T = tile_size(q);
+    g.n = n;
+    g.NT = (n + 1 + T - 1) / T;
+    g.ld = g.NT * T;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    g.codes_bytes = up((size_t)g.NT * T + 64);
+    g.F_bytes = up((size_t)g.ld * g.ld * sizeof(int16_t));
+    g.state_bytes = up((size_t)tile_count(g.NT) * state_words(q) * sizeof(uint32_t));
+    g.bytes = g.codes_bytes + g.F_bytes + 2 * g.state_bytes;
+    return g;
+}
+
+static int between_target()
+{
+    static int t = [] {
+        const char* e = getenv("NF_BETWEEN_TARGET");
+        int v = e ? atoi(e) : 0;
+        return v > 0 ? v : 1024;
+    }();
+    return t;
+}
+
+// Append the between-group items of diagonal dd for the listed folds.  The
+// intermediate tiles C in [A+2, A+dd-2] of every tile are cut into chunks of
+// about equal work so that the step has roughly `target` workgroups; chunk
+// results go to consecutive partial slots starting at *next_slot.
+void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, int target,
+                    std::vector<BetweenItem>& out, int* next_slot,
+                    std::vector<std::vector<std::pair<int, int>>>& pending)
+{
+    if (dd < 4) return;
+    long long W = 0;
+    for (auto& fn : folds_nt)
+        if (fn.second > dd) W += (long long)(fn.second - dd) * (dd - 3);
+    if (W == 0) return;
+    const long long chunk = std::max<long long>(1, (W + target - 1) / target);
+    const int nC = dd - 3;
+    const int ns = (int)((nC + chunk - 1) / chunk);
+    for (auto& fn : folds_nt) {
+        const int f = fn.first, NT = fn.second;
+        if (NT <= dd) continue;
+        auto& pend = pending[f];
+        pend.assign(NT - dd, {0, 0});
+        for (int A = 0; A < NT - dd; ++A) {
+            const int slot0 = *next_slot;
+            for (int s = 0; s < ns; ++s) {
+                BetweenItem it{};
+                it.fold = f;
+                it.A = A;
+                it.d = dd;
+                it.c0 = A + 2 + (int)((long long)s * nC / ns);
+                it.c1 = A + 2 + (int)((long long)(s + 1) * nC / ns);
+                it.slot = (*next_slot)++;
+                out.push_back(it);
+            }
+            pend[A] = {slot0, ns};
+        }
+    }
+}
+
+void build_schedule(const std::vector<int>& NTs, Schedule& sc)
+{
+    const int nf = (int)NTs.size();
+    int stages = 0;
+    for (int v : NTs) stages = std::max(stages, v);
+    sc = Schedule{};
+    sc.stages = stages;
+    sc.tile_off.assign(stages, 0);
+    sc.tile_cnt.assign(stages, 0);
+    sc.btw_off.assign(stages, 0);
+    sc.btw_cnt.assign(stages, 0);
+    std::vector<std::vector<std::pair<int, int>>> pending(nf);
+    std::vector<int> btw_stage_local;  // local slot per between item
+    std::vector<int> btw_stage;        // stage of each between item
+    std::vector<int> tile_stage;
+    std::vector<std::pair<int, int>> folds_nt;
+    folds_nt.reserve(nf);
+    for (int f = 0; f < nf; ++f) folds_nt.push_back({f, NTs[f]});
+    const int target = between_target();
+    int max_slots = 0;
+    for (int sg = 0; sg < stages; ++sg) {
+        if (sg == 0) {
+            for (int f = 0; f < nf; ++f)
+                for (int A = 0; A < NTs[f]; ++A) sc.diag.push_back(TileItem{f, A, 0, 0, 0, 0, 0, 0});
+        } else {
+            sc.tile_off[sg] = (int)sc.tile.size();
+            for (int f = 0; f < nf; ++f) {
+                if (NTs[f] <= sg) continue;
+                for (int A = 0; A < NTs[f] - sg; ++A) {
+                    TileItem it{f, A, sg, 0, 0, 0, 0, 0};
+                    if (sg >= 4) {
+                        it.slot0 = pending[f][A].first;
+                        it.nslot = pending[f][A].second;
+                    }
+                    sc.tile.push_back(it);
+                    tile_stage.push_back(sg);
+                }
+            }
+            sc.tile_cnt[sg] = (int)sc.tile.size() - sc.tile_off[sg];
+        }
+        sc.btw_off[sg] = (int)sc.btw.size();
+        int local = 0;
+        append_between(folds_nt, sg + 1, target, sc.btw, &local, pending);
+        sc.btw_cnt[sg] = (int)sc.btw.size() - sc.btw_off[sg];
+        for (int k = 0; k < sc.btw_cnt[sg]; ++k) btw_stage.push_back(sg);
+        max_slots = std::max(max_slots, local);
+    }
+    // Partial slots are double-buffered by stage parity: the items of stage s
+    // write half (s & 1) while the tiles of stage s read what stage s-1 wrote.
+    sc.max_slots = max_slots;
+    for (size_t k = 0; k < sc.btw.size(); ++k) sc.btw[k].slot += (btw_stage[k] & 1) * max_slots;
+    for (size_t k = 0; k < sc.tile.size(); ++k)
+        if (sc.tile[k].nslot > 0) sc.tile[k].slot0 += ((tile_stage[k] - 1) & 1) * max_slots;
+}
+
+// ------------------------------------------------------------------ plans
+
+Plan::~Plan() { release_graph(); }
+
+void Plan::release_graph()
+{
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+}
+
+static bool use_graphs()
+{
+    static bool g = [] {
+        const char* e = getenv("NF_GRAPH");
+        return !(e && e[0] == '0');
+    }();
+    return g;
+}
+
+// Allocate the device side of a plan whose geoms and schedule are set.
+int plan_allocate(Plan& p)
+{
+    size_t arena = 0;
+    for (auto& g : p.geom) arena += g.bytes;
+    int rc = p.arena.alloc(arena);
+    if (rc) return rc;
+    std::vector<FoldDesc> fd(p.geom.size());
+    size_t off = 0;
+    char* base = (char*)p.arena.p;
+    for (size_t f = 0; f < p.geom.size(); ++f) {
+        const Geom& g = p.geom[f];
+        fd[f].codes = (const uint8_t*)(base + off);
+        fd[f].F = (int16_t*)(base + off + g.codes_bytes);
+        fd[f].RS = (uint32_t*)(base + off + g.codes_bytes + g.F_bytes);
+        fd[f].CS = (uint32_t*)(base + off + g.codes_bytes + g.F_bytes + g.state_bytes);
+        fd[f].n = g.n;
+        fd[f].NT = g.NT;
+        fd[f].ld = g.ld;
+        p.geom[f].codes_off = off;
+        off += g.bytes;
+    }
+    p.h_folds = fd;
+    const Schedule& sc = p.sc;
+    if ((rc = p.d_folds.alloc(fd.size() * sizeof(FoldDesc)))) return rc;
+    if ((rc = p.d_diag.alloc(std::max<size_t>(1, sc.diag.size()) * sizeof(TileItem)))) return rc;
+    if ((rc = p.d_tile.alloc(std::max<size_t>(1, sc.tile.size()) * sizeof(TileItem)))) return rc;
+    if ((rc = p.d_btw.alloc(std::max<size_t>(1, sc.btw.size()) * sizeof(BetweenItem)))) return rc;
+    if ((rc = p.d_part.alloc(std::max<size_t>(1, (size_t)2 * sc.max_slots) * kTileCells * sizeof(int32_t))))
+        return rc;
+    if ((rc = p.d_scores.alloc(std::max<size_t>(1, fd.size()) * sizeof(int32_t)))) return rc;
+    hipStream_t s = ctx().stream;
+    HIPCHK(hipMemcpyAsync(p.d_folds.p, fd.data(), fd.size() * sizeof(FoldDesc), hipMemcpyHostToDevice, s));
+    if (!sc.diag.empty())
+        HIPCHK(hipMemcpyAsync(p.d_diag.p, sc.diag.data(), sc.diag.size() * sizeof(TileItem),
+                              hipMemcpyHostToDevice, s));
+    if (!sc.tile.empty())
+        HIPCHK(hipMemcpyAsync(p.d_tile.p, sc.tile.data(), sc.tile.size() * sizeof(TileItem),
+                              hipMemcpyHostToDevice, s));
+    if (!sc.btw.empty())
+        HIPCHK(hipMemcpyAsync(p.d_btw.p, sc.btw.data(), sc.btw.size() * sizeof(BetweenItem),
+                              hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    p.device_bytes = p.arena.bytes + p.d_folds.bytes + p.d_diag.bytes + p.d_tile.bytes + p.d_btw.bytes +
+                     p.d_part.bytes + p.d_scores.bytes;
+    return NF_OK;
+}
+
+// The fill of every fold in the plan: diagonal tiles, then per stage the
+// tile finishes of diagonal s and the between-group work of diagonal s+1.
+int plan_enqueue_direct(Plan& p, hipStream_t s)
+{
+    const uint8_t* R = nullptr;
+    int rc = get_R(p.q, &R);
+    if (rc) return rc;
+    const FoldDesc* folds = (const FoldDesc*)p.d_folds.p;
+    int32_t* part = (int32_t*)p.d_part.p;
+    const Schedule& sc = p.sc;
+    HIPCHK(launch_diag(p.q, folds, (const TileItem*)p.d_diag.p, (int)sc.diag.size(), s));
+    for (int sg = 0; sg < sc.stages; ++sg) {
+        if (sg >= 1 && sc.tile_cnt[sg] > 0)
+            HIPCHK(launch_tile(p.q, folds, (const TileItem*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R,
+                               part, s));
+        if (sc.btw_cnt[sg] > 0)
+            HIPCHK(launch_between(p.q, folds, (const BetweenItem*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg],
+                                  R, part, s));
+    }
+    HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, s));
+    return NF_OK;
+}
+
+// Valid (non-padding) columns of tile column B of a fold.
+static int valid_cols(const Geom& g, int T, int B) { return std::max(0, std::min(T, g.n + 1 - B * T)); }
+
+int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
+{
+    const uint8_t* R = nullptr;
+    int rc = get_R(p.q, &R);
+    if (rc) return rc;
+    const int T = tile_size(p.q), G = groups_per_tile(p.q);
+    const FoldDesc* folds = (const FoldDesc*)p.d_folds.p;
+    int32_t* part = (int32_t*)p.d_part.p;
+    const Schedule& sc = p.sc;
+    // algorithmic work per launch, from the work lists
+    std::vector<double> tile_lk(sc.stages, 0), tile_cells(sc.stages, 0), btw_lk(sc.stages, 0);
+    for (int sg = 0; sg < sc.stages; ++sg) {
+        for (int k = 0; k < sc.tile_cnt[sg]; ++k) {
+            const TileItem& it = sc.tile[sc.tile_off[sg] + k];
+            const int vb = valid_cols(p.geom[it.fold], T, it.A + it.d);
+            tile_lk[sg] += (double)std::min(std::max(it.d - 1, 0), 2) * G * T * vb;
+            tile_cells[sg] += (double)T * vb;
+        }
+        for (int k = 0; k < sc.btw_cnt[sg]; ++k) {
+            const BetweenItem& it = sc.btw[sc.btw_off[sg] + k];
+            const int vb = valid_cols(p.geom[it.fold], T, it.A + it.d);
+            btw_lk[sg] += (double)(it.c1 - it.c0) * G * T * vb;
+        }
+    }
+    double diag_cells = 0;
+    for (auto& it : sc.diag) {
+        const int v = valid_cols(p.geom[it.fold], T, it.A);
+        diag_cells += (double)v * (v + 1) / 2;
+    }
+    std::vector<hipEvent_t> ev;
+    auto fresh = [&]() {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return (hipEvent_t) nullptr;
+        ev.push_back(e);
+        return e;
+    };
+    struct Rec { int kind; hipEvent_t a, b; double lk, cells; };
+    std::vector<Rec> recs;
+    for (int r = 0; r < reps; ++r) {
+        hipEvent_t a = fresh(), b = fresh();
+        HIPCHK(hipEventRecord(a, s));
+        HIPCHK(launch_diag(p.q, folds, (const TileItem*)p.d_diag.p, (int)sc.diag.size(), s));
+        HIPCHK(hipEventRecord(b, s));
+        recs.push_back({0, a, b, 0.0, diag_cells});
+        for (int sg = 0; sg < sc.stages; ++sg) {
+            if (sg >= 1 && sc.tile_cnt[sg] > 0) {
+                a = fresh(); b = fresh();
+                HIPCHK(hipEventRecord(a, s));
+                HIPCHK(launch_tile(p.q, folds, (const TileItem*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R,
+                                   part, s));
+                HIPCHK(hipEventRecord(b, s));
+                recs.push_back({1, a, b, tile_lk[sg], tile_cells[sg]});
+            }
+            if (sc.btw_cnt[sg] > 0) {
+                a = fresh(); b = fresh();
+                HIPCHK(hipEventRecord(a, s));
+                HIPCHK(launch_between(p.q, folds, (const BetweenItem*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg],
+                                      R, part, s));
+                HIPCHK(hipEventRecord(b, s));
+                recs.push_back({2, a, b, btw_lk[sg], 0.0});
+            }
+        }
+        HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (auto& rc2 : recs) {
+        float ms = 0;
+        if (!rc2.a || !rc2.b) return fail(NF_E_DEVICE, "event creation failed");
+        HIPCHK(hipEventElapsedTime(&ms, rc2.a, rc2.b));
+        out->launches[rc2.kind] += 1;
+        out->ms[rc2.kind] += ms;
+        out->lookups[rc2.kind] += rc2.lk;
+        out->cells[rc2.kind] += rc2.cells;
+    }
+    for (auto e : ev) (void)hipEventDestroy(e);
+    return NF_OK;
+}
+
+int plan_enqueue(Plan& p, hipStream_t s)
+{
+    if (!use_graphs()) return plan_enqueue_direct(p, s);
+    if (!p.exec) {
+        const uint8_t* R = nullptr;
+        int rc = get_R(p.q, &R);  // outside the capture
+        if (rc) return rc;
+        hipStream_t cs = ctx().capture_stream;
+        HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        rc = plan_enqueue_direct(p, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(NF_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        p.graph = g;
+        e = hipGraphInstantiate(&p.exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            p.release_graph();
+            return fail(NF_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+        }
+    }
+    HIPCHK(hipGraphLaunch(p.exec, s));
+    return NF_OK;
+}
+
+int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out)
+{
+    auto p = std::make_unique<Plan>();
+    p->q = q;
+    std::vector<int> NTs;
+    for (int n : ns) {
+        p->geom.push_back(make_geom(n, q));
+        NTs.push_back(p->geom.back().NT);
+    }
+    build_schedule(NTs, p->sc);
+    int rc = plan_allocate(*p);
+    if (rc) return rc;
+    out = std::move(p);
+    return NF_OK;
+}
+
+// Single-fold plans are cached by (n, q), least recently used first out.
+int single_plan(int n, int q, Plan** out)
+{
+    Context& c = ctx();
+    const long long key = (long long)n * 16 + q;
+    for (auto it = c.plans.begin(); it != c.plans.end(); ++it) {
+        if (it->first == key) {
+            auto ent = std::move(*it);
+            c.plans.erase(it);
+            c.plans.push_back(std::move(ent));
+            *out = c.plans.back().second.get();
+            return NF_OK;
+        }
+    }
+    size_t cap = (size_t)8 << 30;
+    if (const char* e = getenv("NF_PLAN_CACHE_BYTES")) cap = strtoull(e, nullptr, 10);
+    const size_t need = make_geom(n, q).bytes;
+    size_t held = 0;
+    for (auto& e : c.plans) held += e.second->device_bytes;
+    while (!c.plans.empty() && held + need > cap) {
+        held -= c.plans.front().second->device_bytes;
+        c.plans.erase(c.plans.begin());
+    }
+    std::unique_ptr<Plan> p;
+    int rc = make_plan({n}, q, p);
+    if (rc == NF_E_NOMEM && !c.plans.empty()) {  // drop every cached plan and retry once
+        c.plans.clear();
+        rc = make_plan({n}, q, p);
+    }
+    if (rc) return rc;
+    c.plans.push_back({key, std::move(p)});
+    *out = c.plans.back().second.get();
+    return NF_OK;
+}
+
+int resolve_q(int q, int n)
+{
+    if (q == 0) return autotune_lookup(n);
+    return q;
+}
+
+int check_q(int q)
+{
+    if (q < 0 || q > NF_Q_MAX) return fail(NF_E_INVAL, "q = %d outside 0..%d", q, NF_Q_MAX);
+    return NF_OK;
+}
+
+// ------------------------------------------------------------------ autotune cache
+
+static int bucket_of(int n)
+{
+    int b = 0;
+    while (b < kTuneBuckets - 1 && n >= (256 << b)) ++b;
+    return b;
+}
+
+static void load_tune_file()
+{
+    Context& c = ctx();
+    if (c.tune_loaded) return;
+    c.tune_loaded = true;
+    const char* path = getenv("NF_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::ifstream in(path);
+    int b, q;
+    while (in >> b >> q)
+        if (b >= 0 && b < kTuneBuckets && q >= NF_Q_MIN && q <= NF_Q_MAX) c.tuned_q[b] = q;
+}
+
+static void save_tune_file()
+{
+    const char* path = getenv("NF_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::ofstream out(path);
+    for (int b = 0; b < kTuneBuckets; ++b)
+        if (ctx().tuned_q[b]) out << b << " " << ctx().tuned_q[b] << "\n";
+}
+
+int autotune_lookup(int n)
+{
+    load_tune_file();
+    const int q = ctx().tuned_q[bucket_of(n)];
+    return q ? q : kDefaultQ;
+}
+
+int autotune_run(int n, int qmin, int qmax, int reps)
+{
+    if (n < 2 || n > NF_MAX_N) return fail(NF_E_INVAL, "autotune length %d out of range", n);
+    qmin = std::max(qmin, NF_Q_MIN);
+    qmax = std::min(qmax, NF_Q_MAX);
+    if (qmin > qmax || reps < 1) return fail(NF_E_INVAL, "empty autotune range");
+    int rc = ensure_device();
+    if (rc) return rc;
+    Context& c = ctx();
+    // a fixed pseudo-random sequence (64-bit LCG), iid over the 4 bases
+    std::vector<uint8_t> codes(n);
+    uint64_t x = 0x9E3779B97F4A7C15ull ^ (uint64_t)n;
+    for (int i = 0; i < n; ++i) {
+        x = x * 6364136223846793005ull + 1442695040888963407ull;
+        codes[i] = (uint8_t)(x >> 62);
+    }
+    int best_q = kDefaultQ;
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int q = qmin; q <= qmax; ++q) {
+        Plan* p = nullptr;
+        if ((rc = single_plan(n, q, &p))) break;
+        const Geom& g = p->geom[0];
+        if (hipMemcpyAsync((char*)p->arena.p + g.codes_off, codes.data(), n, hipMemcpyHostToDevice, c.stream) !=
+            hipSuccess) {
+            rc = fail(NF_E_DEVICE, "autotune upload failed");
+            break;
+        }
+        if ((rc = plan_enqueue(*p, c.stream))) break;  // warm-up (and graph capture)
+        (void)hipEventRecord(e0, c.stream);
+        for (int r = 0; r < reps && !rc; ++r) rc = plan_enqueue(*p, c.stream);
+        (void)hipEventRecord(e1, c.stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (!rc && ms < best_ms) {
+            best_ms = ms;
+            best_q = q;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    load_tune_file();
+    c.tuned_q[bucket_of(n)] = best_q;
+    save_tune_file();
+    return best_q;
+}
+
+}  // namespace nf

@@ -1,0 +1,118 @@
+// Host-side internals of libnf (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <memory>
+#include <utility>
+#include <vector>
+
+#include "nf.h"
+#include "nf_internal.h"
+
+namespace nf {
+
+int fail(int code, const char* fmt, ...);
+const char* last_error();
+void clear_error();
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            (void)hipGetLastError();                                                              \
+            return ::nf::fail(NF_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+        }                                                                                         \
+    } while (0)
+
+// Owned device allocation.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf();
+    int alloc(size_t nbytes);
+    void reset();
+};
+
+// Device layout of one fold (see nf_internal.h).
+struct Geom {
+    int n = 0, NT = 0, ld = 0;
+    size_t codes_bytes = 0, F_bytes = 0, state_bytes = 0, bytes = 0;
+    size_t codes_off = 0;  // offset of this fold's block in its arena
+};
+
+// Packed wavefront schedule of a group of folds that start together: stage s
+// finishes the tiles of diagonal s of every fold that has one and does the
+// between-group work of diagonal s+1.
+struct Schedule {
+    int stages = 0;
+    int max_slots = 0;  // partial slots per parity half
+    std::vector<TileItem> diag;
+    std::vector<TileItem> tile;
+    std::vector<BetweenItem> btw;
+    std::vector<int> tile_off, tile_cnt, btw_off, btw_cnt;
+};
+
+struct Plan {
+    int q = 8;
+    std::vector<Geom> geom;
+    std::vector<FoldDesc> h_folds;
+    Schedule sc;
+    DevBuf arena, d_folds, d_diag, d_tile, d_btw, d_part, d_scores;
+    DevBuf d_S;  // expand target for host copies of tables
+    size_t device_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~Plan();
+    void release_graph();
+};
+
+constexpr int kTuneBuckets = 10;  // n < 256, < 512, ..., >= 65536
+constexpr int kDefaultQ = 8;
+
+struct Context {
+    bool ready = false;
+    int requested_device = 0;
+    int device = 0;
+    int num_cu = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    DevBuf R[NF_Q_MAX + 1];
+    std::vector<std::pair<long long, std::unique_ptr<Plan>>> plans;  // LRU, most recent last
+    int tuned_q[kTuneBuckets] = {0};
+    bool tune_loaded = false;
+};
+
+Context& ctx();
+int ensure_device();
+int get_R(int q, const uint8_t** out);
+int encode_sequence(const char* seq, int n, uint8_t* out);
+int check_length(int n);
+int check_q(int q);
+int resolve_q(int q, int n);
+Geom make_geom(int n, int q);
+void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, int target,
+                    std::vector<BetweenItem>& out, int* next_slot,
+                    std::vector<std::vector<std::pair<int, int>>>& pending);
+void build_schedule(const std::vector<int>& NTs, Schedule& sc);
+int plan_allocate(Plan& p);
+int plan_enqueue(Plan& p, hipStream_t s);
+int plan_enqueue_direct(Plan& p, hipStream_t s);
+int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out);
+int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out);
+int single_plan(int n, int q, Plan** out);
+int autotune_lookup(int n);
+int autotune_run(int n, int qmin, int qmax, int reps);
+
+// serving engine (nf_serve.cpp)
+int serve_config(size_t budget, int max_slots, int max_queue);
+int64_t serve_submit(const char* seq, int n, int q, int want_table);
+int serve_poll(int64_t ticket, int32_t* score_out, int16_t* S_out, int timeout_ms, bool blocking);
+int serve_stats(nf_serve_stats_t* out);
+void serve_shutdown();
+
+}  // namespace nf

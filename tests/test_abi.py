@@ -1,0 +1,57 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching a device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nf.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(nf_[A-Za-z_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1307_7820_amd import nf
+    return nf.load()
+
+
+def test_header_and_binding_agree():
+    from paper_1307_7820_amd import nf
+    assert sorted(nf.EXPORTS) == _declared_functions()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_rejects_bad_input_without_device(lib):
+    from paper_1307_7820_amd import nf
+    # validation happens before any device call
+    assert lib.nf_fold(b"ACGT", 4, 0, None) == nf.NF_E_INVAL
+    assert "0x54" in nf.last_error()
+    assert lib.nf_fold(b"ACGU", 4, 9, None) == nf.NF_E_INVAL
+    assert lib.nf_fold(b"ACGU", -1, 0, None) == nf.NF_E_INVAL
+    assert lib.nf_fold(b"A", nf.NF_MAX_N + 1, 0, None) == nf.NF_E_TOOLONG
+    assert lib.nf_precompute_R(0) == nf.NF_E_INVAL
+    assert lib.nf_precompute_R(9) == nf.NF_E_INVAL
+    buf = (ctypes.c_uint8 * 4)()
+    assert lib.nf_copy_R(3, ctypes.addressof(buf), 4) == nf.NF_E_INVAL  # needs 16 bytes
+
+
+def test_fold_bytes_is_host_arithmetic(lib):
+    from paper_1307_7820_amd import nf
+    b8 = nf.nf_fold_bytes(16000, 8)
+    # dense int16 table of (NT*64)^2 cells dominates: about 516 MB at n = 16000
+    assert 500e6 < b8 < 700e6
+    assert nf.nf_fold_bytes(100, 8) < nf.nf_fold_bytes(1000, 8)
+    assert nf.nf_fold_bytes(-1, 8) == 0

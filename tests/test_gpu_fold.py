@@ -1,0 +1,157 @@
+"""GPU parity: every table the HIP path returns equals the CPU oracle's.
+
+Scores and tables are integers, so the bar is bit-exact equality everywhere.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1307_7820_amd import gen
+from pins import au_closed_form_table, lemma1_violations
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nf():
+    from paper_1307_7820_amd import nf as m
+    m.nf_init(0)
+    return m
+
+
+def _fold_both(nf, s, q):
+    score, T = nf.nf_fold(s, q=q, table=True)
+    want = oracle.fold_table(s)
+    return score, T, want
+
+
+@pytest.mark.parametrize("q", range(1, 9))
+def test_R_table(nf, q):
+    got = nf.nf_copy_R(q)
+    assert np.array_equal(got, oracle.r_table(q))
+
+
+def test_trivial_lengths(nf):
+    for s in ["", "A", "G", "AU", "GU", "GC", "AAA", "ACU"]:
+        score, T = nf.nf_fold(s, q=8, table=True)
+        assert score == oracle.fold_score(s), s
+        assert np.array_equal(T, oracle.fold_table(s).astype(np.int16)), s
+
+
+# lengths around one, two and several tiles (T = 64/q*q <= 64 posts), with
+# ragged tails, for every q
+SIZES = [2, 3, 5, 17, 62, 63, 64, 65, 127, 128, 129, 200, 255, 256, 257, 320, 383, 449, 511, 600]
+
+
+@pytest.mark.parametrize("q", range(1, 9))
+def test_full_tables_all_q(nf, q):
+    for k, n in enumerate(SIZES):
+        s = gen.iid_sequence(n, [101, q, k])
+        score, T, want = _fold_both(nf, s, q)
+        assert score == int(want[0, n - 1]), (q, n)
+        bad = np.argwhere(T != want)
+        assert bad.size == 0, (q, n, bad[:5].tolist())
+
+
+def test_n500_every_q(nf):
+    s = gen.workload_n500()
+    want = oracle.fold_table(s)
+    for q in range(1, 9):
+        score, T = nf.nf_fold(s, q=q, table=True)
+        assert np.array_equal(T, want), q
+        assert score == int(want[0, -1])
+
+
+def test_random_lengths(nf):
+    rng = np.random.default_rng([103])
+    for t in range(40):
+        n = int(rng.integers(2, 700))
+        q = int(rng.integers(1, 9))
+        s = gen.iid_sequence(n, [104, t])
+        score, T, want = _fold_both(nf, s, q)
+        assert np.array_equal(T, want), (n, q)
+
+
+def test_structured_and_biased(nf):
+    for t, s in enumerate([gen.stem_sequence(900, [105, 0]),
+                           gen.iid_sequence(700, [105, 1], probs=(0.45, 0.05, 0.05, 0.45)),
+                           "A" * 300 + "U" * 300, "GC" * 260]):
+        score, T, want = _fold_both(nf, s, 8)
+        assert np.array_equal(T, want), t
+
+
+def test_n6000_full_table(nf):
+    s = gen.workload_n6000()
+    want = oracle.fold_table(s)
+    for q in (0, 8, 4):
+        score, T = nf.nf_fold(s, q=q, table=True)
+        assert score == int(want[0, -1]), q
+        assert np.array_equal(T, want), q
+
+
+def test_n16000_full_table(nf):
+    s = gen.workload_n16000()
+    score, T = nf.nf_fold(s, q=8, table=True)
+    assert lemma1_violations(T) == 0
+    want = oracle.fold_table(s)
+    assert score == int(want[0, -1])
+    assert np.array_equal(T, want)
+
+
+def test_n16000_two_letter_closed_form(nf):
+    # a full-size table pinned without any DP: min(#A, #U) in every cell
+    s = gen.iid_sequence(16000, [106, 0], probs=(0.5, 0.0, 0.0, 0.5))
+    score, T = nf.nf_fold(s, q=8, table=True)
+    assert np.array_equal(T, au_closed_form_table(s).astype(np.int16))
+
+
+def test_fold_dev_matches_host_api(nf):
+    import torch
+    s = gen.iid_sequence(1000, [107, 0])
+    codes = torch.from_numpy(nf.encode(s)).cuda()
+    d_score = torch.zeros(1, dtype=torch.int32, device="cuda")
+    d_S = torch.full((1000, 1000), -7, dtype=torch.int16, device="cuda")
+    nf.nf_fold_dev(codes, 1000, 8, d_score, d_S, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    want = oracle.fold_table(s)
+    assert int(d_score.item()) == int(want[0, -1])
+    assert np.array_equal(d_S.cpu().numpy(), want)
+
+
+def test_batch_matches_oracle_and_alone(nf):
+    rng = np.random.default_rng([108])
+    seqs = [gen.iid_sequence(int(rng.integers(0, 700)), [109, t]) for t in range(120)]
+    seqs += ["", "A", "AU"]
+    scores, tables = nf.nf_fold_batch(seqs, q=8, tables=True)
+    for s, sc, T in zip(seqs, scores, tables):
+        want = oracle.fold_table(s)
+        assert np.array_equal(T, want), len(s)
+        if len(s):
+            assert sc == int(want[0, -1])
+        alone = nf.nf_fold(s, q=8)
+        assert alone == sc
+
+
+def test_batch_reruns_identical(nf):
+    seqs = gen.batch_sequences(300, 50, 2000, (110, 0))
+    b = nf.Batch(seqs, q=8)
+    b.run()
+    s1 = b.scores().copy()
+    b.run()
+    b.run()
+    s2 = b.scores()
+    assert np.array_equal(s1, s2)
+    for i in (0, 7, 123, 299):
+        assert s1[i] == oracle.fold_score(seqs[i])
+    b.close()
+
+
+def test_errors(nf):
+    with pytest.raises(nf.NFError) as e:
+        nf.nf_fold("ACGT")
+    assert e.value.code == nf.NF_E_INVAL
+    with pytest.raises(nf.NFError):
+        nf.nf_fold("ACGU", q=12)
