@@ -50,7 +50,11 @@ void nf_shutdown(void)
     for (auto& r : c.R) r.reset();
     if (c.stream) (void)hipStreamDestroy(c.stream);
     if (c.capture_stream) (void)hipStreamDestroy(c.capture_stream);
-    c.stream = c.capture_stream = nullptr;
+    if (c.side_stream) (void)hipStreamDestroy(c.side_stream);
+    if (c.ev_tile) (void)hipEventDestroy(c.ev_tile);
+    if (c.ev_btw) (void)hipEventDestroy(c.ev_btw);
+    c.stream = c.capture_stream = c.side_stream = nullptr;
+    c.ev_tile = c.ev_btw = nullptr;
     c.ready = false;
 }
 

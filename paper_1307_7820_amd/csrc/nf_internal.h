@@ -57,26 +57,40 @@ struct FoldDesc {
     int n, NT, ld, pad;
 };
 
-// Between-group work: tile (A, A+d) of fold `fold`, split groups of the
-// tiles C in [c0, c1) (A < c0 <= C < c1 <= A+d), result = one 64x64 int32
-// partial maximum written to partial slot `slot`.
+// Between-group work (host form): tile (A, A+d) of fold `fold`, the groups
+// of the tiles C in [c0, c1) (A < c0 <= C < c1 < A+d).  The 64x64 maxima go
+// to the tile's accumulator slot `slot`; pad0 != 0 when several items share
+// that slot (combined with atomic max).
 struct BetweenItem {
     int fold, A, d, c0, c1, slot, pad0, pad1;
 };
 
-// Tile finish: tile (A, A+d) of fold `fold`; when nslot > 0 the partial
-// maxima in slots [slot0, slot0+nslot) are folded in first.
+// Tile finish (host form): tile (A, A+d) of fold `fold`; when nslot > 0 the
+// accumulator slot slot0 holds between-group maxima to fold in (and is
+// cleared after reading).
 struct TileItem {
     int fold, A, d, slot0, nslot, pad0, pad1, pad2;
 };
 
+// Device-side work items: the fold's descriptor travels inside the item, so a
+// workgroup reaches its data with a single dependent load.
+struct TileWork {
+    FoldDesc f;
+    int A, d, slot0, nslot;
+};
+struct BetweenWork {
+    FoldDesc f;
+    int A, d, c0, c1, slot, atomic, pad0, pad1;
+};
+static_assert(sizeof(TileWork) == 64, "TileWork layout");
+static_assert(sizeof(BetweenWork) == 80, "BetweenWork layout");
+
 hipError_t launch_precompute_R(int q, uint8_t* R, hipStream_t s);
 hipError_t launch_copy_codes(const uint8_t* src, int n, uint8_t* dst, int padded, hipStream_t s);
-hipError_t launch_diag(int q, const FoldDesc* folds, const TileItem* items, int nitems, hipStream_t s);
-hipError_t launch_tile(int q, const FoldDesc* folds, const TileItem* items, int nitems,
-                       const uint8_t* R, const int32_t* part, hipStream_t s);
-hipError_t launch_between(int q, const FoldDesc* folds, const BetweenItem* items, int nitems,
-                          const uint8_t* R, int32_t* part, hipStream_t s);
+hipError_t launch_diag(int q, const TileWork* items, int nitems, hipStream_t s);
+hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, int32_t* acc, hipStream_t s);
+hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, int32_t* acc,
+                          hipStream_t s);
 hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s);
 hipError_t launch_expand(const int16_t* F, int ld, int n, int16_t* S, hipStream_t s);
 

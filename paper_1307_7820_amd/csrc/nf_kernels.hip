@@ -54,8 +54,8 @@ __device__ __forceinline__ void load_R(uint8_t* Rl, const uint8_t* __restrict__ 
 // For group k of tile C the row word comes from tile (A, C) and the column
 // word from tile (C, B); Eq. 3 turns the q split points of the group into
 //     F(a, Cq') + F(Cq', b) + R[h][c].
-template <int Q>
-__device__ __forceinline__ void between_accumulate(int (&acc)[kRowsPerWave], const uint8_t* Rl,
+template <int Q, int RPW>
+__device__ __forceinline__ void between_accumulate(int (&acc)[RPW], const uint8_t* Rl,
                                                    const uint32_t* __restrict__ RS,
                                                    const uint32_t* __restrict__ CS, int NT, int A,
                                                    int B, int c0, int c1, int r0, int j)
@@ -71,7 +71,7 @@ __device__ __forceinline__ void between_accumulate(int (&acc)[kRowsPerWave], con
             const uint32_t clo = cw & 0xffffu;
             const uint32_t chi = cw >> 16;
 #pragma unroll
-            for (int r = 0; r < kRowsPerWave; ++r) {
+            for (int r = 0; r < RPW; ++r) {
                 const uint32_t rw = rs[k * 64 + r];
                 const int v = Rl[(rw & 0xffffu) + clo];
                 acc[r] = max(acc[r], (int)((rw >> 16) + chi) + v);
@@ -105,16 +105,15 @@ __global__ void k_copy_codes(const uint8_t* __restrict__ src, int n, uint8_t* __
 // Main-diagonal tiles (A, A): every split point lies inside the tile, so the
 // tile is filled by its own diagonals t = b - a = 2..T-1 (Eq. 1 directly).
 template <int Q>
-__global__ __launch_bounds__(kThreads) void k_diag(const FoldDesc* __restrict__ folds,
-                                                   const TileItem* __restrict__ items)
+__global__ __launch_bounds__(kThreads) void k_diag(const TileWork* __restrict__ items)
 {
     constexpr int T = tile_size(Q);
     constexpr int XS = 65;  // padded stride: rows of a column are in distinct banks
     __shared__ int32_t X[64 * XS];
     __shared__ uint8_t ca[64], cb[64];
 
-    const TileItem it = items[blockIdx.x];
-    const FoldDesc f = folds[it.fold];
+    const TileWork it = items[blockIdx.x];
+    const FoldDesc& f = it.f;
     const int aT = it.A * T;
     const int tid = threadIdx.x;
 
@@ -144,8 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(const FoldDesc* __restrict__ 
 }
 
 template <int Q>
-__global__ __launch_bounds__(kThreads) void k_between(const FoldDesc* __restrict__ folds,
-                                                      const BetweenItem* __restrict__ items,
+__global__ __launch_bounds__(kThreads) void k_between(const BetweenWork* __restrict__ items,
                                                       const uint8_t* __restrict__ Rg,
                                                       int32_t* __restrict__ part)
 {
@@ -153,8 +151,8 @@ __global__ __launch_bounds__(kThreads) void k_between(const FoldDesc* __restrict
     constexpr int RSZ = 1 << (2 * M);
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
 
-    const BetweenItem it = items[blockIdx.x];
-    const FoldDesc f = folds[it.fold];
+    const BetweenWork it = items[blockIdx.x];
+    const FoldDesc& f = it.f;
     load_R<RSZ>(Rl, Rg);
     __syncthreads();
 
@@ -164,94 +162,200 @@ __global__ __launch_bounds__(kThreads) void k_between(const FoldDesc* __restrict
     int acc[kRowsPerWave];
 #pragma unroll
     for (int r = 0; r < kRowsPerWave; ++r) acc[r] = 0;
-    between_accumulate<Q>(acc, Rl, f.RS, f.CS, f.NT, it.A, it.A + it.d, it.c0, it.c1, r0, j);
+    between_accumulate<Q, kRowsPerWave>(acc, Rl, f.RS, f.CS, f.NT, it.A, it.A + it.d, it.c0, it.c1, r0, j);
 
-    int32_t* out = part + (size_t)it.slot * kTileCells;
+    int32_t* out = part + (size_t)it.slot * kTileCells + r0 * 64 + j;
+    if (it.atomic) {  // several items share the tile's accumulator
 #pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r) out[(r0 + r) * 64 + j] = acc[r];
+        for (int r = 0; r < kRowsPerWave; ++r) atomicMax(out + r * 64, acc[r]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kRowsPerWave; ++r) out[r * 64] = acc[r];
+    }
 }
 
-// Finish of an off-diagonal tile (A, B), B > A.  Lane j owns column j; wave w
-// owns rows 16w..16w+15 and keeps their accumulators in registers.
+// Finish of an off-diagonal tile (A, B), B > A, by 8 wavefronts (512 threads).
 //
 // Inside the tile, with L(i, i') = F(AT+i, AT+i') (tile (A, A)) and
-// U(j', j) = F(BT+j', BT+j) (tile (B, B)), cell (i, j) still needs
-//     splits in tile A:  L(i, i') + X(i', j)   for i < i' < T,
-//     splits in tile B:  X(i, j') + U(j', j)   for 0 <= j' < j,
-//     pairing:           b(S_{a+1}, S_b) + F(a+1, b-1).
-// X(i, j) depends only on cells with a smaller step t = j + (T-1-i); at
-// iteration s every open cell takes the (at most one) row and (at most one)
-// column term whose source lies on step s-1, then the cells of step s are
-// final and are published in LDS.
+// U(j', j) = F(BT+j', BT+j) (tile (B, B)), cell X(i, j) = F(AT+i, BT+j) is
+//     max{ P(i, j),                                 between groups, in acc
+//          b(S_{a+1}, S_b) + X(i+1, j-1),            pairing
+//          max_{i < i' < T} L(i, i') + X(i', j),     splits inside tile A
+//          max_{0 <= j' < j} X(i, j') + U(j', j) }   splits inside tile B.
+// The last term only involves row i.  Eq. 1 makes F superadditive
+// (F(m1, m3) >= F(m1, m2) + F(m2, m3), since m2 is one of its split points),
+// so chains of U terms never beat a single one and the row recurrence has the
+// closed form  X(i, .) = Q(i, .) (max,+) (I + U),  Q = the first three terms.
+// Rows are finished bottom-up, one max-plus vector-matrix product per row:
+// wave w reduces the split points j' in [8w, 8w+8) (its slice of U sits in
+// registers) and the eight partial maxima are combined in LDS.
+//
+// Wave w owns the accumulators of the 8-row block [8w, 8w+8); lane j is
+// column j.  A finished row is pushed (its L terms) into the rows above it in
+// its own block one split at a time; when a whole block is finished and q
+// divides 8, its q-groups are pushed into every row above the block with one
+// R lookup per group (Eq. 3, row words of tile (A, A), column words of this
+// tile).  For other q every row is pushed one split at a time.
+constexpr int kTileThreads = 512;
+constexpr int kNeg = -(1 << 20);  // stands for minus infinity; sums stay far from overflow
+
 template <int Q>
-__global__ __launch_bounds__(kThreads) void k_tile(const FoldDesc* __restrict__ folds,
-                                                   const TileItem* __restrict__ items,
-                                                   const uint8_t* __restrict__ Rg,
-                                                   const int32_t* __restrict__ part)
+__device__ __forceinline__ int rlookup(const uint8_t* Rl, uint32_t rw, uint32_t cw)
+{
+    return (int)((rw >> 16) + (cw >> 16)) + (int)Rl[(rw & 0xffffu) + (cw & 0xffffu)];
+}
+
+__device__ __forceinline__ int max8(const int4 a, const int4 b)
+{
+    return max(max(max(a.x, a.y), max(a.z, a.w)), max(max(b.x, b.y), max(b.z, b.w)));
+}
+
+template <int Q>
+__global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restrict__ items,
+                                                       const uint8_t* __restrict__ Rg,
+                                                       int32_t* __restrict__ accbuf)
 {
     constexpr int M = Q - 1;
     constexpr int G = groups_per_tile(Q);
     constexpr int T = tile_size(Q);
     constexpr int RSZ = 1 << (2 * M);
     constexpr int SW = state_words(Q);
+    constexpr int RPW = 8;                      // rows per wavefront
+    constexpr bool kBlockFR = (8 % Q) == 0;     // q-groups tile the 8-row blocks
+    constexpr int GPB = kBlockFR ? 8 / Q : 1;   // groups per block
+    constexpr bool kStageEdges = G <= 16;       // end-tile words fit in LDS
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
-    __shared__ __align__(16) int32_t X[64 * 64];
-    __shared__ __align__(16) int16_t Ls[64 * 64];
-    __shared__ __align__(16) int16_t Us[64 * 64];
+    __shared__ __align__(16) int32_t Xs[64 * 64];  // finished cells
+    __shared__ __align__(16) int32_t Lt[64 * 64];  // Lt[i*64 + i''] = L(i'', i) for i'' < i < T, else -inf
+    __shared__ __align__(16) uint32_t LW[kBlockFR ? G * 64 : 4];  // row words of tile (A, A), [k][row]
+    __shared__ __align__(16) uint32_t EW[kStageEdges ? 4 * G * 64 : 4];  // [edge][row|col][k][64]
+    __shared__ __align__(16) int32_t Qs[2][64];    // Q of the row being closed (double-buffered)
+    __shared__ __align__(16) int32_t Ps[64 * 8];   // closure partials, Ps[j*8 + w]
     __shared__ int32_t hrow[64], hcol[64];
     __shared__ uint8_t ca[64], cb[64];
 
-    const TileItem it = items[blockIdx.x];
-    const FoldDesc f = folds[it.fold];
+    const TileWork it = items[blockIdx.x];
+    const FoldDesc& f = it.f;
     const int A = it.A, d = it.d, B = A + d;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int j = tid & 63;
-    const int r0 = wave * kRowsPerWave;
+    const int r0 = wave * RPW;
     const long long ld = f.ld;
     const int aT = A * T, bT = B * T;
     const int16_t* F = f.F;
+    const int nedge = d >= 3 ? 2 : (d == 2 ? 1 : 0);
 
-    load_R<RSZ>(Rl, Rg);
-    for (int e = tid; e < 64 * 64; e += kThreads) {
-        const int i = e >> 6, jj = e & 63;
-        if (i < T && jj < T) {
-            Ls[e] = F[(aT + i) * ld + aT + jj];
-            Us[e] = F[(bT + i) * ld + bT + jj];
+    // ---- prologue: every load issued before the first wait
+    int lv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int e = tid + u * kTileThreads;
+        const int ip = e >> 6, i = e & 63;  // row ip of L, read coalesced
+        lv[u] = (ip < i && i < T) ? (int)F[(aT + ip) * ld + aT + i] : kNeg;
+    }
+    int ureg[8];  // U(8w + c, j); -inf where the split point is not left of column j
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int jp = r0 + c;
+        ureg[c] = (jp <= j && j < T) ? (int)F[(bT + jp) * ld + bT + j] : kNeg;
+    }
+    int acc[RPW];
+    int32_t* accp = accbuf + (size_t)it.slot0 * kTileCells + r0 * 64 + j;
+    if (it.nslot > 0) {
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) acc[r] = accp[r * 64];
+    } else {
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) acc[r] = 0;
+    }
+    if constexpr (RSZ >= 16) {
+        for (int x = tid * 16; x < RSZ; x += kTileThreads * 16)
+            *reinterpret_cast<uint4*>(Rl + x) = *reinterpret_cast<const uint4*>(Rg + x);
+    } else {
+        if (tid < RSZ) Rl[tid] = Rg[tid];
+    }
+    if constexpr (kStageEdges) {
+        // edge e: C = A+1 (e = 0) and C = B-1 (e = 1); row words of (A, C), column words of (C, B)
+        for (int x = tid; x < nedge * 2 * G * 16; x += kTileThreads) {
+            const int e = x / (2 * G * 16), rem = x % (2 * G * 16);
+            const int rc = rem / (G * 16), o = rem % (G * 16);
+            const int C = e == 0 ? A + 1 : B - 1;
+            const uint32_t* src = rc == 0 ? f.RS + tile_index(f.NT, A, C - A) * SW
+                                          : f.CS + tile_index(f.NT, C, B - C) * SW;
+            *reinterpret_cast<uint4*>(&EW[(e * 2 + rc) * G * 64 + o * 4]) =
+                *reinterpret_cast<const uint4*>(src + o * 4);
         }
     }
     if (tid < 64) {
         if (tid < T) {
-            // halo: F((A+1)T, BT-1+j) and F(AT+1+i, BT-1); below the diagonal = 0
-            const int hr_r = aT + T, hr_c = bT - 1 + tid;
+            const int hr_r = aT + T, hr_c = bT - 1 + tid;  // F((A+1)T, BT-1+j)
             hrow[tid] = hr_c >= hr_r ? F[hr_r * ld + hr_c] : 0;
-            const int hc_r = aT + 1 + tid, hc_c = bT - 1;
+            const int hc_r = aT + 1 + tid, hc_c = bT - 1;  // F(AT+1+i, BT-1)
             hcol[tid] = hc_c >= hc_r ? F[hc_r * ld + hc_c] : 0;
         }
         ca[tid] = f.codes[aT + tid];      // S_{a+1}, a = AT + i
-        cb[tid] = f.codes[bT + tid - 1];  // S_b,     b = BT + j   (BT >= 1)
+        cb[tid] = f.codes[bT + tid - 1];  // S_b,     b = BT + j  (BT >= 1)
     }
-
-    int acc[kRowsPerWave];
 #pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r) acc[r] = 0;
-    for (int s = 0; s < it.nslot; ++s) {
-        const int32_t* p = part + (size_t)(it.slot0 + s) * kTileCells + r0 * 64 + j;
+    for (int u = 0; u < 8; ++u) {
+        const int e = tid + u * kTileThreads;
+        Lt[(e & 63) * 64 + (e >> 6)] = lv[u];
+    }
+    if (it.nslot > 0) {  // hand the accumulator back zeroed for its next use
 #pragma unroll
-        for (int r = 0; r < kRowsPerWave; ++r) acc[r] = max(acc[r], p[r * 64]);
+        for (int r = 0; r < RPW; ++r) accp[r * 64] = 0;
     }
     __syncthreads();
 
-    // groups of the intermediate tiles next to the ends: C = A+1 and C = B-1
-    if (d >= 2) between_accumulate<Q>(acc, Rl, f.RS, f.CS, f.NT, A, B, A + 1, A + 2, r0, j);
-    if (d >= 3) between_accumulate<Q>(acc, Rl, f.RS, f.CS, f.NT, A, B, B - 1, B, r0, j);
+    // ---- row words of tile (A, A) for the block pushes
+    if constexpr (kBlockFR) {
+        for (int x = tid; x < G * 64; x += kTileThreads) {
+            const int k = x >> 6, i = x & 63;
+            const int top = k * Q;
+            uint32_t h = 0;
+            int base = 0;
+            if (top > i && top < T) {
+                base = Lt[top * 64 + i];
+#pragma unroll
+                for (int p = 1; p <= M; ++p)
+                    h |= (uint32_t)(Lt[(top + p) * 64 + i] > Lt[(top + p - 1) * 64 + i]) << (p - 1);
+            }
+            LW[x] = ((uint32_t)base << 16) | (h << M);
+        }
+    }
 
-    // pairing bits of this lane's cells; pairing terms whose partner cell
-    // lies outside the tile (last row, first column) come from the halo
+    // ---- groups of the two end tiles C = A+1 and C = B-1
+    if constexpr (kStageEdges) {
+        for (int e = 0; e < nedge; ++e) {
+            const uint32_t* er = &EW[(e * 2 + 0) * G * 64];
+            const uint32_t* ec = &EW[(e * 2 + 1) * G * 64];
+#pragma unroll 2
+            for (int k = 0; k < G; ++k) {
+                const uint32_t cw = ec[k * 64 + j];
+                const uint4 ra = *reinterpret_cast<const uint4*>(&er[k * 64 + r0]);
+                const uint4 rb = *reinterpret_cast<const uint4*>(&er[k * 64 + r0 + 4]);
+                acc[0] = max(acc[0], rlookup<Q>(Rl, ra.x, cw));
+                acc[1] = max(acc[1], rlookup<Q>(Rl, ra.y, cw));
+                acc[2] = max(acc[2], rlookup<Q>(Rl, ra.z, cw));
+                acc[3] = max(acc[3], rlookup<Q>(Rl, ra.w, cw));
+                acc[4] = max(acc[4], rlookup<Q>(Rl, rb.x, cw));
+                acc[5] = max(acc[5], rlookup<Q>(Rl, rb.y, cw));
+                acc[6] = max(acc[6], rlookup<Q>(Rl, rb.z, cw));
+                acc[7] = max(acc[7], rlookup<Q>(Rl, rb.w, cw));
+            }
+        }
+    } else {
+        if (d >= 2) between_accumulate<Q, RPW>(acc, Rl, f.RS, f.CS, f.NT, A, B, A + 1, A + 2, r0, j);
+        if (d >= 3) between_accumulate<Q, RPW>(acc, Rl, f.RS, f.CS, f.NT, A, B, B - 1, B, r0, j);
+    }
+
+    // pairing bits of this lane's rows; pairing terms whose partner lies
+    // outside the tile (last row, first column) come from the halo
     const int cbj = cb[j];
     uint32_t pmask = 0;
 #pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r) {
+    for (int r = 0; r < RPW; ++r) {
         const int i = r0 + r;
         if (i < T && j < T) {
             const int bp = (ca[i] + cbj == 3) ? 1 : 0;
@@ -261,57 +365,140 @@ __global__ __launch_bounds__(kThreads) void k_tile(const FoldDesc* __restrict__ 
         }
     }
 
-    for (int s = 0; s <= 2 * T - 2; ++s) {
+    // ---- rows bottom-up.  Rows >= T (only when T < 64) are inert: their
+    // pushes are -inf in Lt and their pairing into row T-1 is skipped.
+    if (wave == 7) Qs[1][j] = acc[7];  // row 63 has no row below it
+    __syncthreads();
+    const int jl = j > 0 ? j - 1 : 0;
+
+#pragma unroll 1
+    for (int blk = 7; blk >= 0; --blk) {
 #pragma unroll
-        for (int r = 0; r < kRowsPerWave; ++r) {
-            const int i = r0 + r;
-            if (i < T && j < T) {
-                if (s >= 1) {
-                    const int jp = s - T + i;   // row source (i, jp) on step s-1
-                    if (jp >= 0 && jp < j) acc[r] = max(acc[r], X[i * 64 + jp] + (int)Us[jp * 64 + j]);
-                    const int ip = j + T - s;   // column source (ip, j) on step s-1
-                    if (ip > i && ip <= T - 1) acc[r] = max(acc[r], (int)Ls[i * 64 + ip] + X[ip * 64 + j]);
+        for (int rr = 7; rr >= 0; --rr) {
+            const int i = blk * 8 + rr;
+            {   // closure partial over j' in [8w, 8w+8)
+                const int4 qa = *reinterpret_cast<const int4*>(&Qs[i & 1][r0]);
+                const int4 qb = *reinterpret_cast<const int4*>(&Qs[i & 1][r0 + 4]);
+                int p = max(max(qa.x + ureg[0], qa.y + ureg[1]), max(qa.z + ureg[2], qa.w + ureg[3]));
+                p = max(p, max(max(qb.x + ureg[4], qb.y + ureg[5]), max(qb.z + ureg[6], qb.w + ureg[7])));
+                Ps[j * 8 + wave] = p;
+            }
+            __syncthreads();
+            if constexpr (kBlockFR) {
+                if (wave == blk) {
+                    // issue every read of this phase before the first wait
+                    const int4 pa = *reinterpret_cast<const int4*>(&Ps[j * 8]);
+                    const int4 pb = *reinterpret_cast<const int4*>(&Ps[j * 8 + 4]);
+                    int4 pla, plb, la, lb;
+                    if (rr > 0) {
+                        pla = *reinterpret_cast<const int4*>(&Ps[jl * 8]);
+                        plb = *reinterpret_cast<const int4*>(&Ps[jl * 8 + 4]);
+                        la = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0]);
+                        lb = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0 + 4]);
+                    }
+                    const int xi = max8(pa, pb);
+                    Xs[i * 64 + j] = xi;
+                    if (rr > 0) {
+                        const int left = max8(pla, plb);
+                        const int lt[8] = {la.x, la.y, la.z, la.w, lb.x, lb.y, lb.z, lb.w};
+#pragma unroll
+                        for (int r = 0; r < 8; ++r)
+                            if (r < rr) acc[r] = max(acc[r], lt[r] + xi);
+                        int qv = acc[rr - 1];
+                        if (i < T && j > 0) qv = max(qv, (int)((pmask >> (rr - 1)) & 1u) + left);
+                        Qs[(i - 1) & 1][j] = qv;
+                    }
                 }
-                if (j + (T - 1) - i == s) {
-                    if (i < T - 1 && j > 0)
-                        acc[r] = max(acc[r], (int)((pmask >> r) & 1) + X[(i + 1) * 64 + j - 1]);
-                    X[i * 64 + j] = acc[r];
+                if (rr == 0 && blk > 0) {
+                    __syncthreads();  // the block's rows are in Xs
+                    if (wave < blk) {
+#pragma unroll
+                        for (int g = 0; g < GPB; ++g) {
+                            const int k = blk * GPB + g;
+                            const int top = k * Q;
+                            uint32_t c = 0;
+#pragma unroll
+                            for (int p = 1; p <= M; ++p)
+                                c |= (uint32_t)(Xs[(top + p - 1) * 64 + j] > Xs[(top + p) * 64 + j]) << (p - 1);
+                            const uint32_t cw = ((uint32_t)Xs[top * 64 + j] << 16) | c;
+                            const uint4 wa = *reinterpret_cast<const uint4*>(&LW[k * 64 + r0]);
+                            const uint4 wb = *reinterpret_cast<const uint4*>(&LW[k * 64 + r0 + 4]);
+                            acc[0] = max(acc[0], rlookup<Q>(Rl, wa.x, cw));
+                            acc[1] = max(acc[1], rlookup<Q>(Rl, wa.y, cw));
+                            acc[2] = max(acc[2], rlookup<Q>(Rl, wa.z, cw));
+                            acc[3] = max(acc[3], rlookup<Q>(Rl, wa.w, cw));
+                            acc[4] = max(acc[4], rlookup<Q>(Rl, wb.x, cw));
+                            acc[5] = max(acc[5], rlookup<Q>(Rl, wb.y, cw));
+                            acc[6] = max(acc[6], rlookup<Q>(Rl, wb.z, cw));
+                            acc[7] = max(acc[7], rlookup<Q>(Rl, wb.w, cw));
+                        }
+                        if (wave == blk - 1) {
+                            const int left = Xs[i * 64 + jl];
+                            int qv = acc[7];
+                            if (i < T && j > 0) qv = max(qv, (int)((pmask >> 7) & 1u) + left);
+                            Qs[(i - 1) & 1][j] = qv;
+                        }
+                    }
+                }
+            } else {
+                const int xi = max8(*reinterpret_cast<const int4*>(&Ps[j * 8]),
+                                    *reinterpret_cast<const int4*>(&Ps[j * 8 + 4]));
+                const int left = max8(*reinterpret_cast<const int4*>(&Ps[jl * 8]),
+                                      *reinterpret_cast<const int4*>(&Ps[jl * 8 + 4]));
+                if (wave == blk) Xs[i * 64 + j] = xi;
+                const int4 la = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0]);
+                const int4 lb = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0 + 4]);
+                acc[0] = max(acc[0], la.x + xi);
+                acc[1] = max(acc[1], la.y + xi);
+                acc[2] = max(acc[2], la.z + xi);
+                acc[3] = max(acc[3], la.w + xi);
+                acc[4] = max(acc[4], lb.x + xi);
+                acc[5] = max(acc[5], lb.y + xi);
+                acc[6] = max(acc[6], lb.z + xi);
+                acc[7] = max(acc[7], lb.w + xi);
+                if (i >= 1) {
+                    const int owner = (rr > 0) ? blk : blk - 1;
+                    const int slot = (rr > 0) ? rr - 1 : 7;
+                    if (wave == owner) {
+                        int qv = acc[slot];
+                        if (i < T && j > 0) qv = max(qv, (int)((pmask >> slot) & 1u) + left);
+                        Qs[(i - 1) & 1][j] = qv;
+                    }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
-    // dense cells, straight from the registers
+    // ---- emit: dense cells, row words (ballot), column words
     int16_t* Fw = f.F;
     const long long t_idx = tile_index(f.NT, A, d);
     uint32_t* RSw = f.RS + t_idx * SW;
     uint32_t* CSw = f.CS + t_idx * SW;
 #pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r) {
+    for (int r = 0; r < RPW; ++r) {
         const int i = r0 + r;
         if (i < T) {
-            const int v = acc[r];
+            const int v = Xs[i * 64 + j];
             if (j < T) Fw[(aT + i) * ld + bT + j] = (int16_t)v;
-            // row words: difference bits of the row by a wave ballot
             const int left = __shfl_up(v, 1);
             const unsigned long long diff = __ballot(j > 0 && j < T && v > left);
             if (j < T && (j % Q) == 0) {
-                const uint32_t h = (uint32_t)(diff >> (j + 1)) & ((1u << M) - 1u);
+                uint32_t h = 0;
+                if constexpr (M > 0) h = (uint32_t)(diff >> (j + 1)) & ((1u << M) - 1u);
                 RSw[(j / Q) * 64 + i] = ((uint32_t)v << 16) | (h << M);
             }
         }
     }
-    // column words from the published cells
-    for (int e = tid; e < G * 64; e += kThreads) {
+    for (int e = tid; e < G * 64; e += kTileThreads) {
         const int k = e >> 6, jj = e & 63;
         if (jj < T) {
             const int top = k * Q;
             uint32_t c = 0;
 #pragma unroll
             for (int p = 1; p <= M; ++p)
-                c |= (uint32_t)(X[(top + p - 1) * 64 + jj] > X[(top + p) * 64 + jj]) << (p - 1);
-            CSw[k * 64 + jj] = ((uint32_t)X[top * 64 + jj] << 16) | c;
+                c |= (uint32_t)(Xs[(top + p - 1) * 64 + jj] > Xs[(top + p) * 64 + jj]) << (p - 1);
+            CSw[k * 64 + jj] = ((uint32_t)Xs[top * 64 + jj] << 16) | c;
         }
     }
 }
@@ -337,32 +524,31 @@ __global__ void k_expand(const int16_t* __restrict__ F, int ld, int n, int16_t* 
 }
 
 template <int Q>
-hipError_t launch_q(int which, const FoldDesc* folds, const void* items, int nitems, const uint8_t* R,
-                    int32_t* part, hipStream_t s)
+hipError_t launch_q(int which, const void* items, int nitems, const uint8_t* R, int32_t* acc, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
     dim3 grid(nitems), block(kThreads);
     if (which == 0)
-        hipLaunchKernelGGL(k_diag<Q>, grid, block, 0, s, folds, (const TileItem*)items);
+        hipLaunchKernelGGL(k_diag<Q>, grid, block, 0, s, (const TileWork*)items);
     else if (which == 1)
-        hipLaunchKernelGGL(k_tile<Q>, grid, block, 0, s, folds, (const TileItem*)items, R, part);
+        hipLaunchKernelGGL(k_tile<Q>, grid, dim3(kTileThreads), 0, s, (const TileWork*)items, R, acc);
     else
-        hipLaunchKernelGGL(k_between<Q>, grid, block, 0, s, folds, (const BetweenItem*)items, R, part);
+        hipLaunchKernelGGL(k_between<Q>, grid, block, 0, s, (const BetweenWork*)items, R, acc);
     return hipGetLastError();
 }
 
-hipError_t dispatch(int q, int which, const FoldDesc* folds, const void* items, int nitems,
-                    const uint8_t* R, int32_t* part, hipStream_t s)
+hipError_t dispatch(int q, int which, const void* items, int nitems, const uint8_t* R, int32_t* acc,
+                    hipStream_t s)
 {
     switch (q) {
-    case 1: return launch_q<1>(which, folds, items, nitems, R, part, s);
-    case 2: return launch_q<2>(which, folds, items, nitems, R, part, s);
-    case 3: return launch_q<3>(which, folds, items, nitems, R, part, s);
-    case 4: return launch_q<4>(which, folds, items, nitems, R, part, s);
-    case 5: return launch_q<5>(which, folds, items, nitems, R, part, s);
-    case 6: return launch_q<6>(which, folds, items, nitems, R, part, s);
-    case 7: return launch_q<7>(which, folds, items, nitems, R, part, s);
-    case 8: return launch_q<8>(which, folds, items, nitems, R, part, s);
+    case 1: return launch_q<1>(which, items, nitems, R, acc, s);
+    case 2: return launch_q<2>(which, items, nitems, R, acc, s);
+    case 3: return launch_q<3>(which, items, nitems, R, acc, s);
+    case 4: return launch_q<4>(which, items, nitems, R, acc, s);
+    case 5: return launch_q<5>(which, items, nitems, R, acc, s);
+    case 6: return launch_q<6>(which, items, nitems, R, acc, s);
+    case 7: return launch_q<7>(which, items, nitems, R, acc, s);
+    case 8: return launch_q<8>(which, items, nitems, R, acc, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -384,21 +570,20 @@ hipError_t launch_copy_codes(const uint8_t* src, int n, uint8_t* dst, int padded
     return hipGetLastError();
 }
 
-hipError_t launch_diag(int q, const FoldDesc* folds, const TileItem* items, int nitems, hipStream_t s)
+hipError_t launch_diag(int q, const TileWork* items, int nitems, hipStream_t s)
 {
-    return dispatch(q, 0, folds, items, nitems, nullptr, nullptr, s);
+    return dispatch(q, 0, items, nitems, nullptr, nullptr, s);
 }
 
-hipError_t launch_tile(int q, const FoldDesc* folds, const TileItem* items, int nitems, const uint8_t* R,
-                       const int32_t* part, hipStream_t s)
+hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, int32_t* acc, hipStream_t s)
 {
-    return dispatch(q, 1, folds, items, nitems, R, const_cast<int32_t*>(part), s);
+    return dispatch(q, 1, items, nitems, R, acc, s);
 }
 
-hipError_t launch_between(int q, const FoldDesc* folds, const BetweenItem* items, int nitems,
-                          const uint8_t* R, int32_t* part, hipStream_t s)
+hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, int32_t* acc,
+                          hipStream_t s)
 {
-    return dispatch(q, 2, folds, items, nitems, R, part, s);
+    return dispatch(q, 2, items, nitems, R, acc, s);
 }
 
 hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s)

@@ -118,6 +118,9 @@ int ensure_device()
     c.num_cu = prop.multiProcessorCount;
     HIPCHK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&c.capture_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&c.side_stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c.ev_tile, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c.ev_btw, hipEventDisableTiming));
     c.ready = true;
     return NF_OK;
 }
@@ -167,8 +170,10 @@ static int between_target()
 
 // Append the between-group items of diagonal dd for the listed folds.  The
 // intermediate tiles C in [A+2, A+dd-2] of every tile are cut into chunks of
-// about equal work so that the step has roughly `target` workgroups; chunk
-// results go to consecutive partial slots starting at *next_slot.
+// about equal work so that the step has roughly `target` workgroups.  Every
+// tile owns one accumulator slot (numbered from *next_slot); when a tile is
+// split its chunks combine there with atomic max, otherwise the single item
+// stores.  The tile finish reads the slot and clears it for its next use.
 void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, int target,
                     std::vector<BetweenItem>& out, int* next_slot,
                     std::vector<std::vector<std::pair<int, int>>>& pending)
@@ -187,7 +192,7 @@ void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, in
         auto& pend = pending[f];
         pend.assign(NT - dd, {0, 0});
         for (int A = 0; A < NT - dd; ++A) {
-            const int slot0 = *next_slot;
+            const int slot = (*next_slot)++;
             for (int s = 0; s < ns; ++s) {
                 BetweenItem it{};
                 it.fold = f;
@@ -195,10 +200,11 @@ void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, in
                 it.d = dd;
                 it.c0 = A + 2 + (int)((long long)s * nC / ns);
                 it.c1 = A + 2 + (int)((long long)(s + 1) * nC / ns);
-                it.slot = (*next_slot)++;
+                it.slot = slot;
+                it.pad0 = ns > 1 ? 1 : 0;
                 out.push_back(it);
             }
-            pend[A] = {slot0, ns};
+            pend[A] = {slot, 1};
         }
     }
 }
@@ -250,8 +256,9 @@ void build_schedule(const std::vector<int>& NTs, Schedule& sc)
         for (int k = 0; k < sc.btw_cnt[sg]; ++k) btw_stage.push_back(sg);
         max_slots = std::max(max_slots, local);
     }
-    // Partial slots are double-buffered by stage parity: the items of stage s
-    // write half (s & 1) while the tiles of stage s read what stage s-1 wrote.
+    // Accumulator slots are double-buffered by stage parity: the items of
+    // stage s write half (s & 1) while the tiles of stage s read (and clear)
+    // what stage s-1 wrote.
     sc.max_slots = max_slots;
     for (size_t k = 0; k < sc.btw.size(); ++k) sc.btw[k].slot += (btw_stage[k] & 1) * max_slots;
     for (size_t k = 0; k < sc.tile.size(); ++k)
@@ -279,6 +286,30 @@ static bool use_graphs()
     return g;
 }
 
+TileWork to_work(const TileItem& it, const std::vector<FoldDesc>& fd)
+{
+    TileWork w{};
+    w.f = fd[it.fold];
+    w.A = it.A;
+    w.d = it.d;
+    w.slot0 = it.slot0;
+    w.nslot = it.nslot;
+    return w;
+}
+
+BetweenWork to_work(const BetweenItem& it, const std::vector<FoldDesc>& fd)
+{
+    BetweenWork w{};
+    w.f = fd[it.fold];
+    w.A = it.A;
+    w.d = it.d;
+    w.c0 = it.c0;
+    w.c1 = it.c1;
+    w.slot = it.slot;
+    w.atomic = it.pad0;
+    return w;
+}
+
 // Allocate the device side of a plan whose geoms and schedule are set.
 int plan_allocate(Plan& p)
 {
@@ -303,24 +334,29 @@ int plan_allocate(Plan& p)
     }
     p.h_folds = fd;
     const Schedule& sc = p.sc;
+    // device work lists with the fold descriptors folded in
+    std::vector<TileWork> wd(sc.diag.size()), wt(sc.tile.size());
+    std::vector<BetweenWork> wb(sc.btw.size());
+    for (size_t k = 0; k < sc.diag.size(); ++k) wd[k] = to_work(sc.diag[k], fd);
+    for (size_t k = 0; k < sc.tile.size(); ++k) wt[k] = to_work(sc.tile[k], fd);
+    for (size_t k = 0; k < sc.btw.size(); ++k) wb[k] = to_work(sc.btw[k], fd);
     if ((rc = p.d_folds.alloc(fd.size() * sizeof(FoldDesc)))) return rc;
-    if ((rc = p.d_diag.alloc(std::max<size_t>(1, sc.diag.size()) * sizeof(TileItem)))) return rc;
-    if ((rc = p.d_tile.alloc(std::max<size_t>(1, sc.tile.size()) * sizeof(TileItem)))) return rc;
-    if ((rc = p.d_btw.alloc(std::max<size_t>(1, sc.btw.size()) * sizeof(BetweenItem)))) return rc;
+    if ((rc = p.d_diag.alloc(std::max<size_t>(1, wd.size()) * sizeof(TileWork)))) return rc;
+    if ((rc = p.d_tile.alloc(std::max<size_t>(1, wt.size()) * sizeof(TileWork)))) return rc;
+    if ((rc = p.d_btw.alloc(std::max<size_t>(1, wb.size()) * sizeof(BetweenWork)))) return rc;
     if ((rc = p.d_part.alloc(std::max<size_t>(1, (size_t)2 * sc.max_slots) * kTileCells * sizeof(int32_t))))
         return rc;
     if ((rc = p.d_scores.alloc(std::max<size_t>(1, fd.size()) * sizeof(int32_t)))) return rc;
     hipStream_t s = ctx().stream;
+    // accumulators start at zero (max with 0 is neutral: every score is >= 0)
+    HIPCHK(hipMemsetAsync(p.d_part.p, 0, p.d_part.bytes, s));
     HIPCHK(hipMemcpyAsync(p.d_folds.p, fd.data(), fd.size() * sizeof(FoldDesc), hipMemcpyHostToDevice, s));
-    if (!sc.diag.empty())
-        HIPCHK(hipMemcpyAsync(p.d_diag.p, sc.diag.data(), sc.diag.size() * sizeof(TileItem),
-                              hipMemcpyHostToDevice, s));
-    if (!sc.tile.empty())
-        HIPCHK(hipMemcpyAsync(p.d_tile.p, sc.tile.data(), sc.tile.size() * sizeof(TileItem),
-                              hipMemcpyHostToDevice, s));
-    if (!sc.btw.empty())
-        HIPCHK(hipMemcpyAsync(p.d_btw.p, sc.btw.data(), sc.btw.size() * sizeof(BetweenItem),
-                              hipMemcpyHostToDevice, s));
+    if (!wd.empty())
+        HIPCHK(hipMemcpyAsync(p.d_diag.p, wd.data(), wd.size() * sizeof(TileWork), hipMemcpyHostToDevice, s));
+    if (!wt.empty())
+        HIPCHK(hipMemcpyAsync(p.d_tile.p, wt.data(), wt.size() * sizeof(TileWork), hipMemcpyHostToDevice, s));
+    if (!wb.empty())
+        HIPCHK(hipMemcpyAsync(p.d_btw.p, wb.data(), wb.size() * sizeof(BetweenWork), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     p.device_bytes = p.arena.bytes + p.d_folds.bytes + p.d_diag.bytes + p.d_tile.bytes + p.d_btw.bytes +
                      p.d_part.bytes + p.d_scores.bytes;
@@ -328,24 +364,43 @@ int plan_allocate(Plan& p)
 }
 
 // The fill of every fold in the plan: diagonal tiles, then per stage the
-// tile finishes of diagonal s and the between-group work of diagonal s+1.
+// tile finishes of diagonal s (on stream s) and, on a second stream, the
+// between-group work of diagonal s+1, which only needs diagonals <= s-1 and
+// so overlaps the finishes.  Events order the two streams:
+//     finish(s)    after between(s-1)  (its between maxima)
+//     between(s)   after finish(s-1)   (its inputs; also frees its accumulators)
+// Under graph capture the events become graph edges.
 int plan_enqueue_direct(Plan& p, hipStream_t s)
 {
     const uint8_t* R = nullptr;
     int rc = get_R(p.q, &R);
     if (rc) return rc;
+    Context& c = ctx();
     const FoldDesc* folds = (const FoldDesc*)p.d_folds.p;
     int32_t* part = (int32_t*)p.d_part.p;
     const Schedule& sc = p.sc;
-    HIPCHK(launch_diag(p.q, folds, (const TileItem*)p.d_diag.p, (int)sc.diag.size(), s));
+    hipStream_t s2 = c.side_stream;
+    hipEvent_t ev_tile = c.ev_tile, ev_btw = c.ev_btw;
+    HIPCHK(hipEventRecord(ev_tile, s));  // fork: s2 starts after the work already on s
     for (int sg = 0; sg < sc.stages; ++sg) {
-        if (sg >= 1 && sc.tile_cnt[sg] > 0)
-            HIPCHK(launch_tile(p.q, folds, (const TileItem*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R,
-                               part, s));
+        if (sg == 0) {
+            HIPCHK(launch_diag(p.q, (const TileWork*)p.d_diag.p, (int)sc.diag.size(), s));
+        } else {
+            HIPCHK(hipStreamWaitEvent(s, ev_btw, 0));  // between(sg-1) done
+            HIPCHK(hipEventRecord(ev_tile, s));         // marks finish(sg-1) done
+            if (sc.tile_cnt[sg] > 0)
+                HIPCHK(launch_tile(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R,
+                                   part, s));
+        }
+        HIPCHK(hipStreamWaitEvent(s2, ev_tile, 0));  // finish(sg-1) done
         if (sc.btw_cnt[sg] > 0)
-            HIPCHK(launch_between(p.q, folds, (const BetweenItem*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg],
-                                  R, part, s));
+            HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R,
+                                  part, s2));
+        HIPCHK(hipEventRecord(ev_btw, s2));
     }
+    // join the side stream back into s
+    HIPCHK(hipEventRecord(ev_btw, s2));
+    HIPCHK(hipStreamWaitEvent(s, ev_btw, 0));
     HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, s));
     return NF_OK;
 }
@@ -394,14 +449,14 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
     for (int r = 0; r < reps; ++r) {
         hipEvent_t a = fresh(), b = fresh();
         HIPCHK(hipEventRecord(a, s));
-        HIPCHK(launch_diag(p.q, folds, (const TileItem*)p.d_diag.p, (int)sc.diag.size(), s));
+        HIPCHK(launch_diag(p.q, (const TileWork*)p.d_diag.p, (int)sc.diag.size(), s));
         HIPCHK(hipEventRecord(b, s));
         recs.push_back({0, a, b, 0.0, diag_cells});
         for (int sg = 0; sg < sc.stages; ++sg) {
             if (sg >= 1 && sc.tile_cnt[sg] > 0) {
                 a = fresh(); b = fresh();
                 HIPCHK(hipEventRecord(a, s));
-                HIPCHK(launch_tile(p.q, folds, (const TileItem*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R,
+                HIPCHK(launch_tile(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R,
                                    part, s));
                 HIPCHK(hipEventRecord(b, s));
                 recs.push_back({1, a, b, tile_lk[sg], tile_cells[sg]});
@@ -409,7 +464,7 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
             if (sc.btw_cnt[sg] > 0) {
                 a = fresh(); b = fresh();
                 HIPCHK(hipEventRecord(a, s));
-                HIPCHK(launch_between(p.q, folds, (const BetweenItem*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg],
+                HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg],
                                       R, part, s));
                 HIPCHK(hipEventRecord(b, s));
                 recs.push_back({2, a, b, btw_lk[sg], 0.0});

@@ -81,6 +81,8 @@ struct Context {
     int num_cu = 0;
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
+    hipStream_t side_stream = nullptr;  // between-group kernels overlap the tile finishes here
+    hipEvent_t ev_tile = nullptr, ev_btw = nullptr;
     DevBuf R[NF_Q_MAX + 1];
     std::vector<std::pair<long long, std::unique_ptr<Plan>>> plans;  // LRU, most recent last
     int tuned_q[kTuneBuckets] = {0};
@@ -100,6 +102,8 @@ void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, in
                     std::vector<std::vector<std::pair<int, int>>>& pending);
 void build_schedule(const std::vector<int>& NTs, Schedule& sc);
 int plan_allocate(Plan& p);
+TileWork to_work(const TileItem& it, const std::vector<FoldDesc>& fd);
+BetweenWork to_work(const BetweenItem& it, const std::vector<FoldDesc>& fd);
 int plan_enqueue(Plan& p, hipStream_t s);
 int plan_enqueue_direct(Plan& p, hipStream_t s);
 int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out);
