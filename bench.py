@@ -157,6 +157,109 @@ def extra_batch(nf, torch, gen, looped_sample: int):
             "speedup_vs_looped": looped_est_ms / ms, "score_checksum": int(scores.sum())}
 
 
+def _pct(xs, p):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), p)) if xs else None
+
+
+def extra_serving(nf, torch, gen, count=600, warm=60, budget=2 << 30):
+    """FIFO single folds (plain) vs the continuous-batching engine (served).
+
+    Same request sequence for both (lengths 80% U{100..500}, 20% U{2000..8000},
+    iid bases).  Saturation: every request available at t=0.  Open loop:
+    Poisson arrivals at 0.8 x the plain saturation rate; latency = completion
+    observed by the caller - arrival.
+    """
+    import threading
+    import numpy as np
+    trace = gen.serving_trace(count + warm, 1.0, seed=(1307, 5))
+    seqs = [s for _, s in trace]
+    stream = torch.cuda.current_stream()
+    codes = [torch.from_numpy(nf.encode(s)).cuda() for s in seqs]
+    d_score = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for c, s in zip(codes, seqs):  # warm every single-fold plan
+        nf.nf_fold_dev(c, len(s), 8, d_score, None, stream)
+    torch.cuda.synchronize()
+    meas = list(range(warm, warm + count))
+
+    def plain_one(i):
+        nf.nf_fold_dev(codes[i], len(seqs[i]), 8, d_score, None, stream)
+        torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    for i in meas:
+        plain_one(i)
+    plain_T = time.perf_counter() - t0
+    mu_plain = count / plain_T
+
+    nf.nf_shutdown()
+    nf.nf_serve_config(budget, 256, 0)
+
+    def served_run(arrivals):
+        tick = {}
+        done_t = {}
+        t_start = time.perf_counter()
+
+        def submitter():
+            for k, i in enumerate(meas):
+                if arrivals is not None:
+                    dt = t_start + arrivals[k] - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                tick[k] = nf.nf_submit(seqs[i], 8)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        outstanding = set()
+        seen = 0
+        while len(done_t) < len(meas):
+            while seen < len(tick):
+                outstanding.add(seen)
+                seen += 1
+            for k in list(outstanding):
+                done, _, _ = nf.nf_poll(tick[k])
+                if done:
+                    done_t[k] = time.perf_counter() - t_start
+                    outstanding.discard(k)
+            time.sleep(0.0001)
+        th.join()
+        return done_t, time.perf_counter() - t_start
+
+    # warm the engine
+    ws = [nf.nf_submit(seqs[i], 8) for i in range(warm)]
+    for t in ws:
+        nf.nf_wait(t, 600000)
+    done_t, served_T = served_run(None)
+    mu_served = count / served_T
+
+    lam = 0.8 * mu_plain
+    rng = np.random.default_rng([1307, 6])
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=count))
+    # plain, open loop: one fold at a time in arrival order
+    lat_plain = []
+    t_start = time.perf_counter()
+    for k, i in enumerate(meas):
+        dt = t_start + arrivals[k] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        plain_one(i)
+        lat_plain.append(time.perf_counter() - t_start - arrivals[k])
+    # served, open loop
+    done_t, _ = served_run(arrivals)
+    lat_served = [done_t[k] - arrivals[k] for k in range(count)]
+    st = nf.nf_serve_stats()
+    nf.nf_shutdown()
+    return {
+        "requests": count, "budget_bytes": budget, "mean_n": float(np.mean([len(seqs[i]) for i in meas])),
+        "saturation_folds_per_s": {"plain_fifo": mu_plain, "served": mu_served},
+        "open_loop_rate_per_s": lam,
+        "latency_ms_plain": {"p50": 1e3 * _pct(lat_plain, 50), "p99": 1e3 * _pct(lat_plain, 99)},
+        "latency_ms_served": {"p50": 1e3 * _pct(lat_served, 50), "p99": 1e3 * _pct(lat_served, 99)},
+        "served_over_plain_throughput": mu_served / mu_plain,
+        "engine_steps": int(st.steps), "peak_bytes": int(st.peak_bytes),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +306,11 @@ def main():
             log("bench: batch %s" % json.dumps(extra["batch4096"]))
         except Exception as e:
             extra["batch4096"] = {"error": repr(e)}
+        try:
+            extra["serving"] = extra_serving(nf, torch, gen)
+            log("bench: serving %s" % json.dumps(extra["serving"]))
+        except Exception as e:
+            extra["serving"] = {"error": repr(e)}
     line = {
         "metric": "Nussinov GCUPS at n=6000/16000; batched folds/s + p99 latency vs plain",
         "value": value, "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

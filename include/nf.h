@@ -137,7 +137,9 @@ int nf_fold_batch(const char* const* seqs, const int* ns, int count, int q,
  * max_queue = pending requests before NF_E_BUSY (0 = 65536). */
 int nf_serve_config(size_t hbm_budget_bytes, int max_slots, int max_queue);
 
-/* Device bytes a fold of length n would hold while active under q. */
+/* Device bytes a fold of length n holds while active in the serving engine
+ * under q (table, packed words, accumulators; a request with want_table holds
+ * n*n*2 more).  0 for arguments out of range. */
 size_t nf_fold_bytes(int n, int q);
 
 /* Queue a fold (the sequence is copied).  Returns a ticket >= 0 or a negative

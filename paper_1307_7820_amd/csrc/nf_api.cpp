@@ -274,7 +274,7 @@ size_t nf_fold_bytes(int n, int q)
         std::lock_guard<std::recursive_mutex> lk(g_api);
         q = resolve_q(0, n);
     }
-    return make_geom(n, q).bytes;
+    return serve_fold_bytes(n, q);
 }
 
 int64_t nf_submit(const char* seq, int n, int q, int want_table)

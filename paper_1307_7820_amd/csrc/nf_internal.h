@@ -74,23 +74,25 @@ struct TileItem {
 
 // Device-side work items: the fold's descriptor travels inside the item, so a
 // workgroup reaches its data with a single dependent load.
+// acc points at the tile's 64x64 int32 accumulator (between-group maxima).
 struct TileWork {
     FoldDesc f;
-    int A, d, slot0, nslot;
+    int32_t* acc;  // read and cleared when nslot > 0
+    int A, d, nslot, pad0, pad1, pad2;
 };
 struct BetweenWork {
     FoldDesc f;
-    int A, d, c0, c1, slot, atomic, pad0, pad1;
+    int32_t* acc;  // combined with atomic max when atomic != 0, else stored
+    int A, d, c0, c1, atomic, pad0;
 };
-static_assert(sizeof(TileWork) == 64, "TileWork layout");
+static_assert(sizeof(TileWork) == 80, "TileWork layout");
 static_assert(sizeof(BetweenWork) == 80, "BetweenWork layout");
 
 hipError_t launch_precompute_R(int q, uint8_t* R, hipStream_t s);
 hipError_t launch_copy_codes(const uint8_t* src, int n, uint8_t* dst, int padded, hipStream_t s);
 hipError_t launch_diag(int q, const TileWork* items, int nitems, hipStream_t s);
-hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, int32_t* acc, hipStream_t s);
-hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, int32_t* acc,
-                          hipStream_t s);
+hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, hipStream_t s);
+hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, hipStream_t s);
 hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s);
 hipError_t launch_expand(const int16_t* F, int ld, int n, int16_t* S, hipStream_t s);
 

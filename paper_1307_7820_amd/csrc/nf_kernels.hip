@@ -144,8 +144,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(const TileWork* __restrict__ 
 
 template <int Q>
 __global__ __launch_bounds__(kThreads) void k_between(const BetweenWork* __restrict__ items,
-                                                      const uint8_t* __restrict__ Rg,
-                                                      int32_t* __restrict__ part)
+                                                      const uint8_t* __restrict__ Rg)
 {
     constexpr int M = Q - 1;
     constexpr int RSZ = 1 << (2 * M);
@@ -164,7 +163,7 @@ __global__ __launch_bounds__(kThreads) void k_between(const BetweenWork* __restr
     for (int r = 0; r < kRowsPerWave; ++r) acc[r] = 0;
     between_accumulate<Q, kRowsPerWave>(acc, Rl, f.RS, f.CS, f.NT, it.A, it.A + it.d, it.c0, it.c1, r0, j);
 
-    int32_t* out = part + (size_t)it.slot * kTileCells + r0 * 64 + j;
+    int32_t* out = it.acc + r0 * 64 + j;
     if (it.atomic) {  // several items share the tile's accumulator
 #pragma unroll
         for (int r = 0; r < kRowsPerWave; ++r) atomicMax(out + r * 64, acc[r]);
@@ -212,8 +211,7 @@ __device__ __forceinline__ int max8(const int4 a, const int4 b)
 
 template <int Q>
 __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restrict__ items,
-                                                       const uint8_t* __restrict__ Rg,
-                                                       int32_t* __restrict__ accbuf)
+                                                       const uint8_t* __restrict__ Rg)
 {
     constexpr int M = Q - 1;
     constexpr int G = groups_per_tile(Q);
@@ -261,7 +259,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
         ureg[c] = (jp <= j && j < T) ? (int)F[(bT + jp) * ld + bT + j] : kNeg;
     }
     int acc[RPW];
-    int32_t* accp = accbuf + (size_t)it.slot0 * kTileCells + r0 * 64 + j;
+    int32_t* accp = it.acc + r0 * 64 + j;
     if (it.nslot > 0) {
 #pragma unroll
         for (int r = 0; r < RPW; ++r) acc[r] = accp[r * 64];
@@ -524,31 +522,30 @@ __global__ void k_expand(const int16_t* __restrict__ F, int ld, int n, int16_t* 
 }
 
 template <int Q>
-hipError_t launch_q(int which, const void* items, int nitems, const uint8_t* R, int32_t* acc, hipStream_t s)
+hipError_t launch_q(int which, const void* items, int nitems, const uint8_t* R, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
     dim3 grid(nitems), block(kThreads);
     if (which == 0)
         hipLaunchKernelGGL(k_diag<Q>, grid, block, 0, s, (const TileWork*)items);
     else if (which == 1)
-        hipLaunchKernelGGL(k_tile<Q>, grid, dim3(kTileThreads), 0, s, (const TileWork*)items, R, acc);
+        hipLaunchKernelGGL(k_tile<Q>, grid, dim3(kTileThreads), 0, s, (const TileWork*)items, R);
     else
-        hipLaunchKernelGGL(k_between<Q>, grid, block, 0, s, (const BetweenWork*)items, R, acc);
+        hipLaunchKernelGGL(k_between<Q>, grid, block, 0, s, (const BetweenWork*)items, R);
     return hipGetLastError();
 }
 
-hipError_t dispatch(int q, int which, const void* items, int nitems, const uint8_t* R, int32_t* acc,
-                    hipStream_t s)
+hipError_t dispatch(int q, int which, const void* items, int nitems, const uint8_t* R, hipStream_t s)
 {
     switch (q) {
-    case 1: return launch_q<1>(which, items, nitems, R, acc, s);
-    case 2: return launch_q<2>(which, items, nitems, R, acc, s);
-    case 3: return launch_q<3>(which, items, nitems, R, acc, s);
-    case 4: return launch_q<4>(which, items, nitems, R, acc, s);
-    case 5: return launch_q<5>(which, items, nitems, R, acc, s);
-    case 6: return launch_q<6>(which, items, nitems, R, acc, s);
-    case 7: return launch_q<7>(which, items, nitems, R, acc, s);
-    case 8: return launch_q<8>(which, items, nitems, R, acc, s);
+    case 1: return launch_q<1>(which, items, nitems, R, s);
+    case 2: return launch_q<2>(which, items, nitems, R, s);
+    case 3: return launch_q<3>(which, items, nitems, R, s);
+    case 4: return launch_q<4>(which, items, nitems, R, s);
+    case 5: return launch_q<5>(which, items, nitems, R, s);
+    case 6: return launch_q<6>(which, items, nitems, R, s);
+    case 7: return launch_q<7>(which, items, nitems, R, s);
+    case 8: return launch_q<8>(which, items, nitems, R, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -572,18 +569,17 @@ hipError_t launch_copy_codes(const uint8_t* src, int n, uint8_t* dst, int padded
 
 hipError_t launch_diag(int q, const TileWork* items, int nitems, hipStream_t s)
 {
-    return dispatch(q, 0, items, nitems, nullptr, nullptr, s);
+    return dispatch(q, 0, items, nitems, nullptr, s);
 }
 
-hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, int32_t* acc, hipStream_t s)
+hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, hipStream_t s)
 {
-    return dispatch(q, 1, items, nitems, R, acc, s);
+    return dispatch(q, 1, items, nitems, R, s);
 }
 
-hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, int32_t* acc,
-                          hipStream_t s)
+hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, hipStream_t s)
 {
-    return dispatch(q, 2, items, nitems, R, acc, s);
+    return dispatch(q, 2, items, nitems, R, s);
 }
 
 hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s)

@@ -286,26 +286,26 @@ static bool use_graphs()
     return g;
 }
 
-TileWork to_work(const TileItem& it, const std::vector<FoldDesc>& fd)
+TileWork to_work(const TileItem& it, const std::vector<FoldDesc>& fd, int32_t* acc_base)
 {
     TileWork w{};
     w.f = fd[it.fold];
+    w.acc = acc_base + (size_t)it.slot0 * kTileCells;
     w.A = it.A;
     w.d = it.d;
-    w.slot0 = it.slot0;
     w.nslot = it.nslot;
     return w;
 }
 
-BetweenWork to_work(const BetweenItem& it, const std::vector<FoldDesc>& fd)
+BetweenWork to_work(const BetweenItem& it, const std::vector<FoldDesc>& fd, int32_t* acc_base)
 {
     BetweenWork w{};
     w.f = fd[it.fold];
+    w.acc = acc_base + (size_t)it.slot * kTileCells;
     w.A = it.A;
     w.d = it.d;
     w.c0 = it.c0;
     w.c1 = it.c1;
-    w.slot = it.slot;
     w.atomic = it.pad0;
     return w;
 }
@@ -334,18 +334,19 @@ int plan_allocate(Plan& p)
     }
     p.h_folds = fd;
     const Schedule& sc = p.sc;
-    // device work lists with the fold descriptors folded in
+    if ((rc = p.d_folds.alloc(fd.size() * sizeof(FoldDesc)))) return rc;
+    if ((rc = p.d_part.alloc(std::max<size_t>(1, (size_t)2 * sc.max_slots) * kTileCells * sizeof(int32_t))))
+        return rc;
+    // device work lists with the fold descriptors and accumulator addresses folded in
+    int32_t* acc_base = (int32_t*)p.d_part.p;
     std::vector<TileWork> wd(sc.diag.size()), wt(sc.tile.size());
     std::vector<BetweenWork> wb(sc.btw.size());
-    for (size_t k = 0; k < sc.diag.size(); ++k) wd[k] = to_work(sc.diag[k], fd);
-    for (size_t k = 0; k < sc.tile.size(); ++k) wt[k] = to_work(sc.tile[k], fd);
-    for (size_t k = 0; k < sc.btw.size(); ++k) wb[k] = to_work(sc.btw[k], fd);
-    if ((rc = p.d_folds.alloc(fd.size() * sizeof(FoldDesc)))) return rc;
+    for (size_t k = 0; k < sc.diag.size(); ++k) wd[k] = to_work(sc.diag[k], fd, acc_base);
+    for (size_t k = 0; k < sc.tile.size(); ++k) wt[k] = to_work(sc.tile[k], fd, acc_base);
+    for (size_t k = 0; k < sc.btw.size(); ++k) wb[k] = to_work(sc.btw[k], fd, acc_base);
     if ((rc = p.d_diag.alloc(std::max<size_t>(1, wd.size()) * sizeof(TileWork)))) return rc;
     if ((rc = p.d_tile.alloc(std::max<size_t>(1, wt.size()) * sizeof(TileWork)))) return rc;
     if ((rc = p.d_btw.alloc(std::max<size_t>(1, wb.size()) * sizeof(BetweenWork)))) return rc;
-    if ((rc = p.d_part.alloc(std::max<size_t>(1, (size_t)2 * sc.max_slots) * kTileCells * sizeof(int32_t))))
-        return rc;
     if ((rc = p.d_scores.alloc(std::max<size_t>(1, fd.size()) * sizeof(int32_t)))) return rc;
     hipStream_t s = ctx().stream;
     // accumulators start at zero (max with 0 is neutral: every score is >= 0)
@@ -377,7 +378,6 @@ int plan_enqueue_direct(Plan& p, hipStream_t s)
     if (rc) return rc;
     Context& c = ctx();
     const FoldDesc* folds = (const FoldDesc*)p.d_folds.p;
-    int32_t* part = (int32_t*)p.d_part.p;
     const Schedule& sc = p.sc;
     hipStream_t s2 = c.side_stream;
     hipEvent_t ev_tile = c.ev_tile, ev_btw = c.ev_btw;
@@ -389,13 +389,11 @@ int plan_enqueue_direct(Plan& p, hipStream_t s)
             HIPCHK(hipStreamWaitEvent(s, ev_btw, 0));  // between(sg-1) done
             HIPCHK(hipEventRecord(ev_tile, s));         // marks finish(sg-1) done
             if (sc.tile_cnt[sg] > 0)
-                HIPCHK(launch_tile(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R,
-                                   part, s));
+                HIPCHK(launch_tile(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R, s));
         }
         HIPCHK(hipStreamWaitEvent(s2, ev_tile, 0));  // finish(sg-1) done
         if (sc.btw_cnt[sg] > 0)
-            HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R,
-                                  part, s2));
+            HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R, s2));
         HIPCHK(hipEventRecord(ev_btw, s2));
     }
     // join the side stream back into s
@@ -415,7 +413,6 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
     if (rc) return rc;
     const int T = tile_size(p.q), G = groups_per_tile(p.q);
     const FoldDesc* folds = (const FoldDesc*)p.d_folds.p;
-    int32_t* part = (int32_t*)p.d_part.p;
     const Schedule& sc = p.sc;
     // algorithmic work per launch, from the work lists
     std::vector<double> tile_lk(sc.stages, 0), tile_cells(sc.stages, 0), btw_lk(sc.stages, 0);
@@ -456,8 +453,7 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
             if (sg >= 1 && sc.tile_cnt[sg] > 0) {
                 a = fresh(); b = fresh();
                 HIPCHK(hipEventRecord(a, s));
-                HIPCHK(launch_tile(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R,
-                                   part, s));
+                HIPCHK(launch_tile(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R, s));
                 HIPCHK(hipEventRecord(b, s));
                 recs.push_back({1, a, b, tile_lk[sg], tile_cells[sg]});
             }
@@ -465,7 +461,7 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
                 a = fresh(); b = fresh();
                 HIPCHK(hipEventRecord(a, s));
                 HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg],
-                                      R, part, s));
+                                      R, s));
                 HIPCHK(hipEventRecord(b, s));
                 recs.push_back({2, a, b, btw_lk[sg], 0.0});
             }

@@ -102,8 +102,8 @@ void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, in
                     std::vector<std::vector<std::pair<int, int>>>& pending);
 void build_schedule(const std::vector<int>& NTs, Schedule& sc);
 int plan_allocate(Plan& p);
-TileWork to_work(const TileItem& it, const std::vector<FoldDesc>& fd);
-BetweenWork to_work(const BetweenItem& it, const std::vector<FoldDesc>& fd);
+TileWork to_work(const TileItem& it, const std::vector<FoldDesc>& fd, int32_t* acc_base);
+BetweenWork to_work(const BetweenItem& it, const std::vector<FoldDesc>& fd, int32_t* acc_base);
 int plan_enqueue(Plan& p, hipStream_t s);
 int plan_enqueue_direct(Plan& p, hipStream_t s);
 int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out);
@@ -118,5 +118,6 @@ int64_t serve_submit(const char* seq, int n, int q, int want_table);
 int serve_poll(int64_t ticket, int32_t* score_out, int16_t* S_out, int timeout_ms, bool blocking);
 int serve_stats(nf_serve_stats_t* out);
 void serve_shutdown();
+size_t serve_fold_bytes(int n, int q);
 
 }  // namespace nf

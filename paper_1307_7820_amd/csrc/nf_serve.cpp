@@ -1,10 +1,712 @@
-// Serving engine: placeholder until the continuous-batching engine lands.
+// Serving engine: continuous batching of folds on one GPU.
+//
+// A background thread owns a device arena of `budget` bytes.  Each device
+// step advances every active fold by one tile diagonal: the finishes of its
+// current diagonal (on stream s1) and the between-group work of its next
+// diagonal (on stream s2, overlapping the finishes, as in a single fold).
+// Requests that arrive while others run are admitted at the next step when a
+// slot and enough arena bytes are free; their codes, table, packed words and
+// accumulators stay in the arena until the fold completes.  A finished fold's
+// score (and table, if asked for) is copied to pinned host memory and the
+// ticket completes when that copy has landed.  Results never depend on which
+// other folds share a step: every fold's kernels read and write only its own
+// arena block, and max is order-free.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
 #include "nf_runtime.h"
 
 namespace nf {
-int serve_config(size_t, int, int) { return fail(NF_E_DEVICE, "serving engine not built"); }
-int64_t serve_submit(const char*, int, int, int) { return fail(NF_E_DEVICE, "serving engine not built"); }
-int serve_poll(int64_t, int32_t*, int16_t*, int, bool) { return fail(NF_E_DEVICE, "serving engine not built"); }
-int serve_stats(nf_serve_stats_t*) { return fail(NF_E_DEVICE, "serving engine not built"); }
-void serve_shutdown() {}
+
+std::recursive_mutex& api_mutex();
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr int kInflightSteps = 2;  // device steps queued ahead of the host
+constexpr int kBypassLimit = 64;   // steps a blocked queue head may be overtaken
+constexpr size_t kAlign = 256;
+
+struct Request {
+    int64_t ticket = 0;
+    std::vector<uint8_t> codes;  // padded to the fold's codes block
+    int n = 0, q = 8;
+    bool want_table = false;
+    size_t bytes = 0;
+};
+
+struct Result {
+    int status = 1;  // 1 = done, < 0 = error code
+    int32_t score = 0;
+    std::vector<int16_t> table;
+};
+
+// First-fit allocator over offsets of one device allocation.
+class Arena {
+public:
+    void reset(size_t cap)
+    {
+        free_.clear();
+        if (cap) free_[0] = cap;
+    }
+    bool alloc(size_t sz, size_t* off)
+    {
+        sz = (sz + kAlign - 1) & ~(kAlign - 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= sz) {
+                *off = it->first;
+                const size_t rest = it->second - sz, at = it->first + sz;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t sz)
+    {
+        sz = (sz + kAlign - 1) & ~(kAlign - 1);
+        auto it = free_.emplace(off, sz).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+private:
+    std::map<size_t, size_t> free_;
+};
+
+struct Active {
+    Request req;
+    Geom g;
+    size_t off = 0;
+    FoldDesc fd{};
+    int32_t* acc = nullptr;  // 2 * NT accumulators, [diagonal parity][A]
+    int16_t* S = nullptr;    // expanded table (want_table)
+    int stage = 0;           // next diagonal to finish
+    int slot = 0;            // index into the pinned score array
+    int16_t* h_table = nullptr;
+};
+
+struct StepRec {
+    hipEvent_t ev = nullptr;
+    std::vector<Active*> finishing;
+    int ring = 0;
+};
+
+struct Engine {
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    size_t budget = 0;
+    int max_slots = 256;
+    int max_queue = 65536;
+    bool configured = false, running = false, stop = false;
+    std::thread th;
+    std::deque<Request> pending;
+    std::unordered_map<int64_t, Result> done;
+    std::unordered_set<int64_t> live;
+    int64_t next_ticket = 1;
+    nf_serve_stats_t st{};
+    size_t held = 0;
+    int head_bypassed = 0;
+};
+
+Engine& eng()
+{
+    static Engine e;
+    return e;
+}
+
+size_t serve_bytes(const Geom& g, bool want_table)
+{
+    size_t b = g.bytes + (size_t)2 * g.NT * kTileCells * sizeof(int32_t);
+    if (want_table) b += (size_t)g.n * g.n * sizeof(int16_t) + kAlign;
+    return b;
+}
+
+size_t default_budget()
+{
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        return (size_t)8 << 30;
+    }
+    return std::min((size_t)(fr * 0.8), (size_t)32 << 30);
+}
+
+// ---------------------------------------------------------------- engine thread
+
+struct Device {
+    DevBuf arena_mem;
+    Arena arena;
+    hipStream_t s1 = nullptr, s2 = nullptr;
+    hipEvent_t ev_tile = nullptr, ev_btw = nullptr;
+    const uint8_t* R[NF_Q_MAX + 1] = {nullptr};
+    // ring of item buffers (pinned staging + device copy)
+    struct Ring {
+        char* host = nullptr;
+        DevBuf dev;
+        size_t cap = 0;
+        hipEvent_t free_ev = nullptr;
+        bool used = false;
+    } ring[kInflightSteps + 1];
+    int32_t* h_scores = nullptr;  // pinned, one per slot
+    DevBuf d_scores;
+    std::vector<int> free_slots;
+};
+
+void fail_all(Engine& E, std::vector<Active*>& active, int code)
+{
+    std::lock_guard<std::mutex> lk(E.mu);
+    for (auto* a : active) {
+        E.done[a->req.ticket] = Result{code, 0, {}};
+        E.live.erase(a->req.ticket);
+    }
+    for (auto& r : E.pending) {
+        E.done[r.ticket] = Result{code, 0, {}};
+        E.live.erase(r.ticket);
+    }
+    E.pending.clear();
+    E.cv_done.notify_all();
+}
+
+int engine_init(Engine& E, Device& D)
+{
+    {
+        std::lock_guard<std::recursive_mutex> lk(api_mutex());
+        int rc = ensure_device();
+        if (rc) return rc;
+    }
+    HIPCHK(hipStreamCreateWithFlags(&D.s1, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&D.s2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&D.ev_tile, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&D.ev_btw, hipEventDisableTiming));
+    int rc = D.arena_mem.alloc(E.budget);
+    if (rc) return rc;
+    D.arena.reset(E.budget);
+    HIPCHK(hipHostMalloc((void**)&D.h_scores, sizeof(int32_t) * E.max_slots, hipHostMallocDefault));
+    if ((rc = D.d_scores.alloc(sizeof(int32_t) * E.max_slots))) return rc;
+    for (int i = E.max_slots - 1; i >= 0; --i) D.free_slots.push_back(i);
+    for (auto& r : D.ring) HIPCHK(hipEventCreateWithFlags(&r.free_ev, hipEventDisableTiming));
+    return NF_OK;
+}
+
+void engine_release(Device& D)
+{
+    if (D.s1) (void)hipStreamSynchronize(D.s1);
+    if (D.s2) (void)hipStreamSynchronize(D.s2);
+    for (auto& r : D.ring) {
+        if (r.host) (void)hipHostFree(r.host);
+        if (r.free_ev) (void)hipEventDestroy(r.free_ev);
+        r.dev.reset();
+    }
+    if (D.h_scores) (void)hipHostFree(D.h_scores);
+    D.d_scores.reset();
+    D.arena_mem.reset();
+    if (D.ev_tile) (void)hipEventDestroy(D.ev_tile);
+    if (D.ev_btw) (void)hipEventDestroy(D.ev_btw);
+    if (D.s1) (void)hipStreamDestroy(D.s1);
+    if (D.s2) (void)hipStreamDestroy(D.s2);
+}
+
+int ensure_ring(Device::Ring& r, size_t bytes)
+{
+    if (r.cap >= bytes) return NF_OK;
+    size_t cap = std::max(bytes, r.cap * 2);
+    if (r.host) (void)hipHostFree(r.host);
+    r.host = nullptr;
+    HIPCHK(hipHostMalloc((void**)&r.host, cap, hipHostMallocDefault));
+    int rc = r.dev.alloc(cap);
+    if (rc) return rc;
+    r.cap = cap;
+    return NF_OK;
+}
+
+// Admit pending requests that fit (FIFO, with bounded overtaking of a head
+// that does not fit).  Called with E.mu held.
+void admit(Engine& E, Device& D, std::vector<Active*>& active, std::vector<Active*>& fresh)
+{
+    const int scan = 32;
+    for (int idx = 0; idx < (int)E.pending.size() && idx < scan && (int)active.size() < E.max_slots;) {
+        Request& r = E.pending[idx];
+        size_t off = 0;
+        if (D.free_slots.empty() || !D.arena.alloc(r.bytes, &off)) {
+            if (idx == 0) {
+                if (++E.head_bypassed > kBypassLimit) break;  // let the head in first
+            }
+            ++idx;
+            continue;
+        }
+        if (idx == 0) E.head_bypassed = 0;
+        auto* a = new Active();
+        a->req = std::move(r);
+        E.pending.erase(E.pending.begin() + idx);
+        a->g = make_geom(a->req.n, a->req.q);
+        a->off = off;
+        char* base = (char*)D.arena_mem.p + off;
+        const Geom& g = a->g;
+        a->fd.codes = (const uint8_t*)base;
+        a->fd.F = (int16_t*)(base + g.codes_bytes);
+        a->fd.RS = (uint32_t*)(base + g.codes_bytes + g.F_bytes);
+        a->fd.CS = (uint32_t*)(base + g.codes_bytes + g.F_bytes + g.state_bytes);
+        a->fd.n = g.n;
+        a->fd.NT = g.NT;
+        a->fd.ld = g.ld;
+        a->acc = (int32_t*)(base + g.bytes);
+        if (a->req.want_table)
+            a->S = (int16_t*)(base + ((g.bytes + (size_t)2 * g.NT * kTileCells * sizeof(int32_t) + kAlign - 1) &
+                                      ~(kAlign - 1)));
+        a->slot = D.free_slots.back();
+        D.free_slots.pop_back();
+        E.held += a->req.bytes;
+        E.st.peak_bytes = std::max(E.st.peak_bytes, E.held);
+        E.st.admitted++;
+        active.push_back(a);
+        fresh.push_back(a);
+    }
+}
+
+// Complete the folds of a finished step.  Called without E.mu.
+void complete(Engine& E, Device& D, StepRec& rec)
+{
+    std::vector<std::pair<int64_t, Result>> out;
+    for (Active* a : rec.finishing) {
+        Result res;
+        res.score = D.h_scores[a->slot];
+        if (a->req.want_table) {
+            const size_t cnt = (size_t)a->req.n * a->req.n;
+            res.table.assign(a->h_table, a->h_table + cnt);
+            (void)hipHostFree(a->h_table);
+        }
+        out.push_back({a->req.ticket, std::move(res)});
+    }
+    std::lock_guard<std::mutex> lk(E.mu);
+    for (Active* a : rec.finishing) {
+        D.arena.release(a->off, a->req.bytes);
+        E.held -= a->req.bytes;
+        D.free_slots.push_back(a->slot);
+        delete a;
+    }
+    for (auto& kv : out) {
+        E.live.erase(kv.first);
+        E.done[kv.first] = std::move(kv.second);
+        E.st.completed++;
+    }
+    E.cv_done.notify_all();
+}
+
+void engine_main()
+{
+    Engine& E = eng();
+    Device D;
+    int rc = engine_init(E, D);
+    std::vector<Active*> active;
+    if (rc) {
+        fail_all(E, active, rc);
+        engine_release(D);
+        return;
+    }
+    std::deque<StepRec> inflight;
+    int ring_next = 0;
+    std::vector<TileWork> wdiag, wtile;
+    std::vector<BetweenWork> wbtw;
+    std::vector<FoldDesc> wfin;
+    const int target = std::max(256, ctx().num_cu * 4);
+
+    for (;;) {
+        std::vector<Active*> fresh;
+        {
+            std::unique_lock<std::mutex> lk(E.mu);
+            if (E.stop) break;
+            admit(E, D, active, fresh);
+            E.st.active = (int64_t)active.size();
+            E.st.pending = (int64_t)E.pending.size();
+            bool steppable = false;
+            for (auto* a : active)
+                if (a->stage < a->g.NT) steppable = true;
+            if (!steppable && inflight.empty()) {
+                E.cv_work.wait_for(lk, std::chrono::milliseconds(50));
+                continue;
+            }
+            if (!steppable) {  // nothing to launch: retire the oldest step
+                lk.unlock();
+                if (hipEventSynchronize(inflight.front().ev) != hipSuccess) {
+                    rc = NF_E_DEVICE;
+                    break;
+                }
+                complete(E, D, inflight.front());
+                (void)hipEventDestroy(inflight.front().ev);
+                D.ring[inflight.front().ring].used = false;
+                inflight.pop_front();
+                continue;
+            }
+        }
+        // R tables for any new q
+        for (auto* a : fresh) {
+            if (!D.R[a->req.q]) {
+                std::lock_guard<std::recursive_mutex> lk(api_mutex());
+                if ((rc = get_R(a->req.q, &D.R[a->req.q]))) break;
+            }
+        }
+        if (rc) break;
+        // bound the host's lead over the device
+        while ((int)inflight.size() >= kInflightSteps) {
+            if (hipEventSynchronize(inflight.front().ev) != hipSuccess) { rc = NF_E_DEVICE; break; }
+            complete(E, D, inflight.front());
+            (void)hipEventDestroy(inflight.front().ev);
+            D.ring[inflight.front().ring].used = false;
+            inflight.pop_front();
+        }
+        if (rc) break;
+        // newly admitted folds: codes in, accumulators cleared
+        bool err = false;
+        for (auto* a : fresh) {
+            if (hipMemcpyAsync((void*)a->fd.codes, a->req.codes.data(), a->req.codes.size(), hipMemcpyHostToDevice,
+                               D.s1) != hipSuccess ||
+                hipMemsetAsync(a->acc, 0, (size_t)2 * a->g.NT * kTileCells * sizeof(int32_t), D.s1) != hipSuccess)
+                err = true;
+        }
+        if (err) { rc = NF_E_DEVICE; break; }
+
+        // ---- work lists of this step
+        wdiag.clear();
+        wtile.clear();
+        wbtw.clear();
+        wfin.clear();
+        StepRec rec;
+        long long W = 0;
+        for (auto* a : active) {
+            const int dd = a->stage + 1;
+            if (a->stage < a->g.NT && dd >= 4 && dd < a->g.NT) W += (long long)(a->g.NT - dd) * (dd - 3);
+        }
+        const long long chunk = std::max<long long>(1, (W + target - 1) / target);
+        std::vector<int> qs;
+        for (auto* a : active) {
+            if (a->stage >= a->g.NT) continue;
+            const int s = a->stage, NT = a->g.NT;
+            if (std::find(qs.begin(), qs.end(), a->req.q) == qs.end()) qs.push_back(a->req.q);
+            if (s == 0) {
+                for (int A = 0; A < NT; ++A) {
+                    TileWork w{};
+                    w.f = a->fd;
+                    w.A = A;
+                    w.d = 0;
+                    w.pad0 = a->req.q;
+                    wdiag.push_back(w);
+                }
+            } else {
+                for (int A = 0; A < NT - s; ++A) {
+                    TileWork w{};
+                    w.f = a->fd;
+                    w.acc = a->acc + ((size_t)((s & 1) * NT + A)) * kTileCells;
+                    w.A = A;
+                    w.d = s;
+                    w.nslot = s >= 4 ? 1 : 0;
+                    w.pad0 = a->req.q;
+                    wtile.push_back(w);
+                }
+            }
+            const int dd = s + 1;
+            if (dd >= 4 && dd < NT) {
+                const int nC = dd - 3;
+                const int ns = (int)((nC + chunk - 1) / chunk);
+                for (int A = 0; A < NT - dd; ++A)
+                    for (int k = 0; k < ns; ++k) {
+                        BetweenWork w{};
+                        w.f = a->fd;
+                        w.acc = a->acc + ((size_t)((dd & 1) * NT + A)) * kTileCells;
+                        w.A = A;
+                        w.d = dd;
+                        w.c0 = A + 2 + (int)((long long)k * nC / ns);
+                        w.c1 = A + 2 + (int)((long long)(k + 1) * nC / ns);
+                        w.atomic = ns > 1 ? 1 : 0;
+                        w.pad0 = a->req.q;
+                        wbtw.push_back(w);
+                    }
+            }
+            if (s + 1 == NT) {
+                rec.finishing.push_back(a);
+                wfin.push_back(a->fd);
+            }
+        }
+        // group each list by q (kernels are specialised per q)
+        auto by_q = [](auto& v) {
+            std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.pad0 < y.pad0; });
+        };
+        by_q(wdiag);
+        by_q(wtile);
+        by_q(wbtw);
+        // ---- upload through the ring
+        Device::Ring& rg = D.ring[ring_next];
+        rec.ring = ring_next;
+        ring_next = (ring_next + 1) % (kInflightSteps + 1);
+        const size_t nb_d = wdiag.size() * sizeof(TileWork), nb_t = wtile.size() * sizeof(TileWork);
+        const size_t nb_b = wbtw.size() * sizeof(BetweenWork), nb_f = wfin.size() * sizeof(FoldDesc);
+        const size_t total = nb_d + nb_t + nb_b + nb_f + 64;
+        if (rg.used) (void)hipEventSynchronize(rg.free_ev);
+        if ((rc = ensure_ring(rg, total))) break;
+        char* h = rg.host;
+        std::memcpy(h, wdiag.data(), nb_d);
+        std::memcpy(h + nb_d, wtile.data(), nb_t);
+        std::memcpy(h + nb_d + nb_t, wbtw.data(), nb_b);
+        std::memcpy(h + nb_d + nb_t + nb_b, wfin.data(), nb_f);
+        char* dv = (char*)rg.dev.p;
+        const TileWork* d_diag = (const TileWork*)dv;
+        const TileWork* d_tile = (const TileWork*)(dv + nb_d);
+        const BetweenWork* d_btw = (const BetweenWork*)(dv + nb_d + nb_t);
+        const FoldDesc* d_fin = (const FoldDesc*)(dv + nb_d + nb_t + nb_b);
+        bool ok = hipMemcpyAsync(dv, h, nb_d + nb_t + nb_b + nb_f, hipMemcpyHostToDevice, D.s1) == hipSuccess;
+        // ---- launches
+        ok = ok && hipStreamWaitEvent(D.s1, D.ev_btw, 0) == hipSuccess;  // previous step's between work
+        ok = ok && hipEventRecord(D.ev_tile, D.s1) == hipSuccess;        // previous finishes + items in place
+        auto launch_groups = [&](auto* dptr, auto& v, int which, hipStream_t st) {
+            size_t b = 0;
+            while (ok && b < v.size()) {
+                size_t e = b;
+                while (e < v.size() && v[e].pad0 == v[b].pad0) ++e;
+                const int q = v[b].pad0;
+                hipError_t he;
+                if (which == 0) he = launch_diag(q, (const TileWork*)dptr + b, (int)(e - b), st);
+                else if (which == 1) he = launch_tile(q, (const TileWork*)dptr + b, (int)(e - b), D.R[q], st);
+                else he = launch_between(q, (const BetweenWork*)dptr + b, (int)(e - b), D.R[q], st);
+                ok = he == hipSuccess;
+                b = e;
+            }
+        };
+        launch_groups(d_diag, wdiag, 0, D.s1);
+        launch_groups(d_tile, wtile, 1, D.s1);
+        ok = ok && hipStreamWaitEvent(D.s2, D.ev_tile, 0) == hipSuccess;
+        launch_groups(d_btw, wbtw, 2, D.s2);
+        ok = ok && hipEventRecord(D.ev_btw, D.s2) == hipSuccess;
+        // finished folds: score (and table) to pinned memory
+        if (ok && !rec.finishing.empty()) {
+            ok = launch_scores(d_fin, (int)wfin.size(), (int32_t*)D.d_scores.p, D.s1) == hipSuccess;
+            for (size_t k = 0; ok && k < rec.finishing.size(); ++k) {
+                Active* a = rec.finishing[k];
+                ok = hipMemcpyAsync(D.h_scores + a->slot, (int32_t*)D.d_scores.p + k, sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, D.s1) == hipSuccess;
+                if (ok && a->req.want_table && a->req.n > 0) {
+                    const size_t cnt = (size_t)a->req.n * a->req.n;
+                    ok = hipHostMalloc((void**)&a->h_table, cnt * sizeof(int16_t), hipHostMallocDefault) ==
+                         hipSuccess;
+                    ok = ok && launch_expand(a->fd.F, a->g.ld, a->req.n, a->S, D.s1) == hipSuccess;
+                    ok = ok && hipMemcpyAsync(a->h_table, a->S, cnt * sizeof(int16_t), hipMemcpyDeviceToHost,
+                                              D.s1) == hipSuccess;
+                } else if (ok && a->req.want_table) {
+                    ok = hipHostMalloc((void**)&a->h_table, 16, hipHostMallocDefault) == hipSuccess;
+                }
+            }
+        }
+        // the step is complete when both streams are through it
+        ok = ok && hipStreamWaitEvent(D.s1, D.ev_btw, 0) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&rec.ev, hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipEventRecord(rec.ev, D.s1) == hipSuccess;
+        ok = ok && hipEventRecord(rg.free_ev, D.s1) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            rc = NF_E_DEVICE;
+            break;
+        }
+        rg.used = true;
+        for (auto* a : active)
+            if (a->stage < a->g.NT) a->stage++;
+        {
+            std::lock_guard<std::mutex> lk(E.mu);
+            E.st.steps++;
+        }
+        // finished folds leave the active set now; they complete with rec
+        active.erase(std::remove_if(active.begin(), active.end(),
+                                    [&](Active* a) {
+                                        return std::find(rec.finishing.begin(), rec.finishing.end(), a) !=
+                                               rec.finishing.end();
+                                    }),
+                     active.end());
+        inflight.push_back(std::move(rec));
+        // opportunistic completion of steps the device has already finished
+        while (!inflight.empty() && hipEventQuery(inflight.front().ev) == hipSuccess) {
+            complete(E, D, inflight.front());
+            (void)hipEventDestroy(inflight.front().ev);
+            D.ring[inflight.front().ring].used = false;
+            inflight.pop_front();
+        }
+    }
+    // drain what is in flight, then fail or abort the rest
+    for (auto& r : inflight) {
+        if (rc == NF_OK && hipEventSynchronize(r.ev) == hipSuccess) {
+            complete(E, D, r);
+        } else {
+            for (auto* a : r.finishing) active.push_back(a);
+        }
+        (void)hipEventDestroy(r.ev);
+    }
+    inflight.clear();
+    const int code = rc ? rc : NF_E_ABORTED;
+    fail_all(E, active, code);
+    for (auto* a : active) {
+        if (a->h_table) (void)hipHostFree(a->h_table);
+        delete a;
+    }
+    engine_release(D);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- API side
+
+int serve_config(size_t budget, int max_slots, int max_queue)
+{
+    Engine& E = eng();
+    std::lock_guard<std::mutex> lk(E.mu);
+    if (E.running) return fail(NF_E_BUSY, "serving engine already running; call nf_shutdown first");
+    if (max_slots < 0 || max_queue < 0) return fail(NF_E_INVAL, "negative limits");
+    E.budget = budget;
+    E.max_slots = max_slots ? max_slots : 256;
+    E.max_queue = max_queue ? max_queue : 65536;
+    E.configured = true;
+    E.st = nf_serve_stats_t{};
+    return NF_OK;
+}
+
+size_t serve_fold_bytes(int n, int q) { return serve_bytes(make_geom(n, q), false); }
+
+int64_t serve_submit(const char* seq, int n, int q, int want_table)
+{
+    int rc = check_length(n);
+    if (rc) return rc;
+    if ((rc = check_q(q))) return rc;
+    if (!seq && n > 0) return fail(NF_E_INVAL, "seq is NULL");
+    Request r;
+    {
+        std::lock_guard<std::recursive_mutex> lk(api_mutex());
+        q = resolve_q(q, n);
+    }
+    Geom g = make_geom(n, q);
+    r.codes.assign(g.codes_bytes, 0);
+    if ((rc = encode_sequence(seq, n, r.codes.data()))) return rc;
+    r.n = n;
+    r.q = q;
+    r.want_table = want_table != 0;
+    r.bytes = serve_bytes(g, r.want_table);
+    Engine& E = eng();
+    std::unique_lock<std::mutex> lk(E.mu);
+    if (!E.running) {
+        if (!E.configured) {
+            E.max_slots = 256;
+            E.max_queue = 65536;
+            E.configured = true;
+            E.st = nf_serve_stats_t{};
+        }
+        if (E.budget == 0) {
+            lk.unlock();
+            size_t b;
+            {
+                std::lock_guard<std::recursive_mutex> alk(api_mutex());
+                rc = ensure_device();
+                b = rc ? 0 : default_budget();
+            }
+            if (rc) return rc;
+            lk.lock();
+            if (E.budget == 0) E.budget = b;
+        }
+    }
+    if (r.bytes > E.budget) {
+        E.st.rejected++;
+        return fail(NF_E_NOMEM, "fold needs %zu device bytes; the serving budget is %zu", r.bytes, E.budget);
+    }
+    if ((int)E.pending.size() >= E.max_queue) {
+        E.st.rejected++;
+        return fail(NF_E_BUSY, "serving queue full (%d requests)", E.max_queue);
+    }
+    if (!E.running) {
+        if (E.th.joinable()) E.th.join();
+        E.stop = false;
+        E.running = true;
+        E.st.budget_bytes = E.budget;
+        E.th = std::thread(engine_main);
+    }
+    r.ticket = E.next_ticket++;
+    const int64_t t = r.ticket;
+    E.live.insert(t);
+    E.pending.push_back(std::move(r));
+    E.st.submitted++;
+    E.cv_work.notify_one();
+    return t;
+}
+
+int serve_poll(int64_t ticket, int32_t* score_out, int16_t* S_out, int timeout_ms, bool blocking)
+{
+    Engine& E = eng();
+    std::unique_lock<std::mutex> lk(E.mu);
+    const auto deadline = Clock::now() + std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms);
+    for (;;) {
+        auto it = E.done.find(ticket);
+        if (it != E.done.end()) {
+            Result res = std::move(it->second);
+            E.done.erase(it);
+            if (res.status < 0) return fail(res.status, "ticket %lld did not complete", (long long)ticket);
+            if (score_out) *score_out = res.score;
+            if (S_out && !res.table.empty()) std::memcpy(S_out, res.table.data(), res.table.size() * sizeof(int16_t));
+            return 1;
+        }
+        if (!E.live.count(ticket)) return fail(NF_E_NOTFOUND, "unknown or released ticket %lld", (long long)ticket);
+        if (!blocking) return 0;
+        if (timeout_ms < 0) {
+            E.cv_done.wait(lk);
+        } else if (E.cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
+            if (E.done.count(ticket)) continue;
+            return fail(NF_E_TIMEOUT, "ticket %lld still pending after %d ms", (long long)ticket, timeout_ms);
+        }
+    }
+}
+
+int serve_stats(nf_serve_stats_t* out)
+{
+    Engine& E = eng();
+    std::lock_guard<std::mutex> lk(E.mu);
+    *out = E.st;
+    out->pending = (int64_t)E.pending.size();
+    out->budget_bytes = E.budget;
+    return NF_OK;
+}
+
+void serve_shutdown()
+{
+    Engine& E = eng();
+    {
+        std::lock_guard<std::mutex> lk(E.mu);
+        if (!E.running && !E.th.joinable()) return;
+        E.stop = true;
+        E.cv_work.notify_all();
+    }
+    if (E.th.joinable()) E.th.join();
+    std::lock_guard<std::mutex> lk(E.mu);
+    E.running = false;
+    E.stop = false;
+    E.configured = false;
+    E.budget = 0;
+    E.held = 0;
+    E.head_bypassed = 0;
+    E.st = nf_serve_stats_t{};
+}
+
 }  // namespace nf

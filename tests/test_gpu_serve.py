@@ -1,0 +1,130 @@
+"""GPU tests of the serving engine (nf_submit / nf_poll / nf_wait).
+
+Continuous batching must not change any result: every fold served in a mix
+equals the same fold run alone and the CPU oracle, bit for bit.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1307_7820_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture()
+def nf():
+    from paper_1307_7820_amd import nf as m
+    m.nf_shutdown()
+    yield m
+    m.nf_shutdown()
+
+
+def _drain(nf, tickets, want_table=None, timeout_s=120):
+    """Poll until every ticket completes; returns {ticket: (score, table)}."""
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t, n in tickets.items():
+            if t in out:
+                continue
+            wt = bool(want_table and want_table.get(t))
+            done, score, S = nf.nf_poll(t, n, wt)
+            if done:
+                out[t] = (score, S)
+        assert time.time() - t0 < timeout_s, "serving did not finish"
+        time.sleep(0.0005)
+    return out
+
+
+def test_mix_equals_alone_and_oracle(nf):
+    nf.nf_serve_config(0, 64, 0)
+    trace = gen.serving_trace(60, 0.0, seed=(201, 0), short=(50, 400), long=(1200, 2600), p_short=0.75)
+    seqs = [s for _, s in trace] + ["", "A", "GC", "ACGU" * 20]
+    tickets, want = {}, {}
+    for k, s in enumerate(seqs):
+        t = nf.nf_submit(s, q=8, want_table=(k % 5 == 0))
+        tickets[t] = len(s)
+        want[t] = (k % 5 == 0)
+    res = _drain(nf, tickets, want)
+    for (t, n), s in zip(tickets.items(), seqs):
+        score, S = res[t]
+        assert score == oracle.fold_score(s), n
+        if want[t]:
+            assert np.array_equal(S, oracle.fold_table(s)), n
+        assert score == nf.nf_fold(s, q=8)  # the same fold alone
+    st = nf.nf_serve_stats()
+    assert st.completed == len(seqs) and st.admitted == len(seqs)
+
+
+def test_budget_binds_and_results_hold(nf):
+    per = nf.nf_fold_bytes(1500, 8)
+    budget = int(per * 2.5) + (4 << 20)   # room for about two long folds at a time
+    nf.nf_serve_config(budget, 0, 0)
+    seqs = [gen.iid_sequence(1500, [202, k]) for k in range(6)] + \
+           [gen.iid_sequence(int(n), [203, k]) for k, n in enumerate(np.linspace(60, 600, 20))]
+    tickets = {nf.nf_submit(s, q=8): len(s) for s in seqs}
+    res = _drain(nf, tickets)
+    for (t, n), s in zip(tickets.items(), seqs):
+        assert res[t][0] == oracle.fold_score(s)
+    st = nf.nf_serve_stats()
+    assert st.peak_bytes <= budget
+    assert st.peak_bytes >= per  # the budget actually held long folds
+
+
+def test_errors_and_timeouts(nf):
+    nf.nf_serve_config(64 << 20, 4, 3)
+    with pytest.raises(nf.NFError) as e:
+        nf.nf_submit(gen.iid_sequence(9000, [204, 0]))       # > 64 MB budget
+    assert e.value.code == nf.NF_E_NOMEM
+    with pytest.raises(nf.NFError) as e:
+        nf.nf_submit("ACGT")
+    assert e.value.code == nf.NF_E_INVAL
+    with pytest.raises(nf.NFError) as e:
+        nf.nf_poll(987654321)
+    assert e.value.code == nf.NF_E_NOTFOUND
+    s = gen.iid_sequence(3000, [204, 1])
+    t = nf.nf_submit(s)
+    # queue of 3: at most a few more fit before NF_E_BUSY
+    extra, busy = [], False
+    for k in range(40):
+        try:
+            extra.append(nf.nf_submit(gen.iid_sequence(3000, [205, k])))
+        except nf.NFError as err:
+            assert err.code == nf.NF_E_BUSY
+            busy = True
+            break
+    assert busy
+    score = nf.nf_wait(t, 60000)
+    assert score == oracle.fold_score(s)
+    with pytest.raises(nf.NFError) as e:     # released on completion
+        nf.nf_poll(t)
+    assert e.value.code == nf.NF_E_NOTFOUND
+    for x in extra:
+        nf.nf_wait(x, 60000)
+
+
+def test_wait_timeout_then_complete(nf):
+    nf.nf_serve_config(0, 0, 0)
+    s = gen.iid_sequence(8000, [206, 0])
+    t = nf.nf_submit(s)
+    with pytest.raises(nf.NFError) as e:
+        nf.nf_wait(t, 0)
+    assert e.value.code == nf.NF_E_TIMEOUT
+    assert nf.nf_wait(t, 120000) == oracle.fold_score(s)
+
+
+def test_shutdown_aborts_or_completes(nf):
+    nf.nf_serve_config(0, 8, 0)
+    seqs = [gen.iid_sequence(2500, [207, k]) for k in range(12)]
+    tickets = [nf.nf_submit(s) for s in seqs]
+    nf.nf_shutdown()
+    for t, s in zip(tickets, seqs):
+        try:
+            done, score, _ = nf.nf_poll(t)
+            assert done and score == oracle.fold_score(s)
+        except nf.NFError as err:
+            assert err.code in (nf.NF_E_ABORTED, nf.NF_E_NOTFOUND)
