@@ -260,6 +260,34 @@ def extra_serving(nf, torch, gen, count=600, warm=60, budget=2 << 30):
     }
 
 
+def run_only(args, torch, gen, nf):
+    """One workload, warm-up then K runs, for rocprofv3 kernel traces and counters."""
+    if args.only == "copy":
+        # plain device-to-device copy of 1 GiB: calibrates FETCH_SIZE / WRITE_SIZE
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1)
+        for _ in range(args.warmup + args.steps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"only": "copy", "bytes_per_copy": x.numel(), "copies": args.warmup + args.steps}))
+        return
+    nf.nf_init(0)
+    if args.only == "batch":
+        seqs = gen.workload_batch4096()
+        b = nf.Batch(seqs, q=8)
+        for _ in range(args.warmup + args.steps):
+            b.run(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        print(json.dumps({"only": "batch", "count": len(seqs), "checksum": int(b.scores().sum())}))
+        return
+    seq = gen.workload_n6000() if args.only == "n6000" else gen.workload_n16000()
+    q = args.q if args.q else 8
+    ms, wall, score, _ = time_fold(nf, torch, seq, q, args.steps, args.warmup)
+    print(json.dumps({"only": args.only, "n": len(seq), "q": q, "ms_per_fold": ms / args.steps,
+                      "gcups": cells(len(seq)) * args.steps / (ms / 1e3) / 1e9, "score": score}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +296,8 @@ def main():
     ap.add_argument("--q", type=int, default=0)
     ap.add_argument("--cpu-budget-s", type=float, default=10.0)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra workloads)")
+    ap.add_argument("--only", choices=["n6000", "n16000", "batch", "copy"],
+                    help="run one workload K times and print a short line (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (a single fold is a "
@@ -278,6 +308,9 @@ def main():
     import torch
     from paper_1307_7820_amd import gen, nf
 
+    if args.only:
+        run_only(args, torch, gen, nf)
+        return
     nf.nf_init(0)
     seq = gen.workload_n6000()
     n = len(seq)

@@ -18,16 +18,18 @@
 //
 // Packed state of a finished off-diagonal tile (A, B) (Lemma 1: neighbours
 // differ by 0 or 1):
-//   row word (group k of the tile's columns, row i):
-//       bits 31..16 = F(a, BT+kq)               (base, Eq. 3 "D(i,l)")
-//       bits 15..0  = h << (q-1), bit p-1 of h = F(a, BT+kq+p) - F(a, BT+kq+p-1)
+//   row state (group k of the tile's columns, row i): two words
+//       base = F(a, BT+kq)                       (Eq. 3 "D(i,l)")
+//       bits = h << (q-1), bit p-1 of h = F(a, BT+kq+p) - F(a, BT+kq+p-1)
 //   column word (group k of the tile's rows, column j):
-//       bits 31..16 = F(AT+kq, b)               (base, Eq. 3 "D(l+1,j)")
+//       bits 31..16 = F(AT+kq, b)                (Eq. 3 "D(l+1,j)")
 //       bits 15..0  = c, bit p-1 of c = F(AT+kq+p-1, b) - F(AT+kq+p, b)
-// Both are stored [k][64] per tile (64 words per group, rows/columns >= T
-// unused), so one group of one tile is one 256-byte line.  With these
-// encodings the Four-Russians step of Eq. 3 for cell (a, b) and group K is
-//     rowbase + colbase + R[(rw & 0xffff) + (cw & 0xffff)].
+// Per tile the row block is [bases: k][64] followed by [bits: k][64] and the
+// column block is [k][64] (rows/columns >= T unused), so one group of one tile
+// is one 256-byte line.  The Four-Russians step of Eq. 3 for cell (a, b) and
+// group K is then
+//     base + (cw >> 16) + R[bits + (cw & 0xffff)]
+// and row words, read wave-uniformly, need no unpacking.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,7 +43,8 @@ constexpr int kTileCells = 64 * 64;
 
 __host__ __device__ constexpr int groups_per_tile(int q) { return 64 / q; }
 __host__ __device__ constexpr int tile_size(int q) { return (64 / q) * q; }
-__host__ __device__ constexpr int state_words(int q) { return (64 / q) * 64; }
+__host__ __device__ constexpr int state_words(int q) { return (64 / q) * 64; }  // column block
+__host__ __device__ constexpr int row_words(int q) { return 2 * state_words(q); }  // row block
 __host__ __device__ inline long long tile_index(int NT, int A, int d)
 {
     return (long long)d * NT - (long long)d * (d - 1) / 2 + A;
@@ -52,8 +55,8 @@ __host__ __device__ inline long long tile_count(int NT) { return (long long)NT *
 struct FoldDesc {
     const uint8_t* codes;  // NT*T + 64 bytes: base codes A0 C1 G2 U3, zero padding
     int16_t* F;            // ld x ld table of F(a, b), ld = NT*T
-    uint32_t* RS;          // row words, tile_count(NT) * state_words(q)
-    uint32_t* CS;          // column words, same size
+    uint32_t* RS;          // row blocks, tile_count(NT) * row_words(q)
+    uint32_t* CS;          // column blocks, tile_count(NT) * state_words(q)
     int n, NT, ld, pad;
 };
 

@@ -62,19 +62,20 @@ __device__ __forceinline__ void between_accumulate(int (&acc)[RPW], const uint8_
 {
     constexpr int G = groups_per_tile(Q);
     constexpr int SW = state_words(Q);
+    constexpr int RW = row_words(Q);
     for (int C = c0; C < c1; ++C) {
-        const NF_CONST uint32_t* rs = as_const(RS + tile_index(NT, A, C - A) * SW + r0);
+        const NF_CONST uint32_t* rb = as_const(RS + tile_index(NT, A, C - A) * RW + r0);  // bases
+        const NF_CONST uint32_t* rh = rb + G * 64;                                         // bits
         const NF_GLOBAL uint32_t* cs = as_global(CS + tile_index(NT, C, B - C) * SW + j);
 #pragma unroll 2
         for (int k = 0; k < G; ++k) {
             const uint32_t cw = cs[k * 64];
             const uint32_t clo = cw & 0xffffu;
-            const uint32_t chi = cw >> 16;
+            const int chi = (int)(cw >> 16);
 #pragma unroll
             for (int r = 0; r < RPW; ++r) {
-                const uint32_t rw = rs[k * 64 + r];
-                const int v = Rl[(rw & 0xffffu) + clo];
-                acc[r] = max(acc[r], (int)((rw >> 16) + chi) + v);
+                const int v = Rl[rh[k * 64 + r] + clo];
+                acc[r] = max(acc[r], (int)rb[k * 64 + r] + chi + v);
             }
         }
     }
@@ -185,16 +186,23 @@ __global__ __launch_bounds__(kThreads) void k_between(const BetweenWork* __restr
 // (F(m1, m3) >= F(m1, m2) + F(m2, m3), since m2 is one of its split points),
 // so chains of U terms never beat a single one and the row recurrence has the
 // closed form  X(i, .) = Q(i, .) (max,+) (I + U),  Q = the first three terms.
-// Rows are finished bottom-up, one max-plus vector-matrix product per row:
-// wave w reduces the split points j' in [8w, 8w+8) (its slice of U sits in
-// registers) and the eight partial maxima are combined in LDS.
+// Rows are finished bottom-up, one max-plus vector-matrix product per row.
 //
-// Wave w owns the accumulators of the 8-row block [8w, 8w+8); lane j is
-// column j.  A finished row is pushed (its L terms) into the rows above it in
-// its own block one split at a time; when a whole block is finished and q
-// divides 8, its q-groups are pushed into every row above the block with one
-// R lookup per group (Eq. 3, row words of tile (A, A), column words of this
-// tile).  For other q every row is pushed one split at a time.
+// Work split: wave w owns the 8 columns J_w = [8w, 8w+8) of every row.  Lane
+// l = 8g + c holds column j = 8w + c and the accumulators of rows
+// 8g..8g+7, and for the closure it reduces the split points j' in
+// [8g, 8g+8) (its 8 entries of U sit in registers); the 8 lanes of a column
+// then combine their partial maxima with a butterfly inside the wavefront
+// (DPP row rotation and the gfx950 16/32-lane swaps).  Each row costs one
+// workgroup barrier: the row's Q is published in LDS before it, the row's
+// cells and the next row's Q after it.  The pairing partner of the first
+// column of a slice lives in the wavefront to the left, so that one term is
+// added by the readers of Q instead.  A finished row is pushed (its L terms)
+// into the rows above it in its 8-row block one split at a time; when a
+// whole block is finished and q divides 8 its q-groups reach every row above
+// the block through one R lookup per group (Eq. 3: row words of tile (A, A),
+// column words of this tile).  For other q every row is pushed one split at
+// a time.
 constexpr int kTileThreads = 512;
 constexpr int kNeg = -(1 << 20);  // stands for minus infinity; sums stay far from overflow
 
@@ -204,9 +212,15 @@ __device__ __forceinline__ int rlookup(const uint8_t* Rl, uint32_t rw, uint32_t 
     return (int)((rw >> 16) + (cw >> 16)) + (int)Rl[(rw & 0xffffu) + (cw & 0xffffu)];
 }
 
-__device__ __forceinline__ int max8(const int4 a, const int4 b)
+// max of v over the 8 lanes l ^ {8, 16, 32} (lanes 8g + c, g = 0..7)
+__device__ __forceinline__ int max_over_groups(int v)
 {
-    return max(max(max(a.x, a.y), max(a.z, a.w)), max(max(b.x, b.y), max(b.z, b.w)));
+    v = max(v, __builtin_amdgcn_update_dpp(kNeg, v, 0x128, 0xF, 0xF, false));  // row_ror:8 = lane ^ 8
+    // the swaps return unsigned words: compare them as signed (-inf is negative)
+    auto p16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);           // {v[l], v[l ^ 16]}
+    v = max((int)p16[0], (int)p16[1]);
+    auto p32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);           // {v[l], v[l ^ 32]}
+    return max((int)p32[0], (int)p32[1]);
 }
 
 template <int Q>
@@ -218,27 +232,29 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
     constexpr int T = tile_size(Q);
     constexpr int RSZ = 1 << (2 * M);
     constexpr int SW = state_words(Q);
-    constexpr int RPW = 8;                      // rows per wavefront
+    constexpr int RW = row_words(Q);
     constexpr bool kBlockFR = (8 % Q) == 0;     // q-groups tile the 8-row blocks
     constexpr int GPB = kBlockFR ? 8 / Q : 1;   // groups per block
     constexpr bool kStageEdges = G <= 16;       // end-tile words fit in LDS
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
-    __shared__ __align__(16) int32_t Xs[64 * 64];  // finished cells
+    __shared__ __align__(16) int32_t Xs[64 * 64];  // finished cells, row-major
     __shared__ __align__(16) int32_t Lt[64 * 64];  // Lt[i*64 + i''] = L(i'', i) for i'' < i < T, else -inf
     __shared__ __align__(16) uint32_t LW[kBlockFR ? G * 64 : 4];  // row words of tile (A, A), [k][row]
-    __shared__ __align__(16) uint32_t EW[kStageEdges ? 4 * G * 64 : 4];  // [edge][row|col][k][64]
+    __shared__ __align__(16) uint32_t EW[kStageEdges ? 6 * G * 64 : 4];  // [edge][base|bits|col][k][64]
     __shared__ __align__(16) int32_t Qs[2][64];    // Q of the row being closed (double-buffered)
-    __shared__ __align__(16) int32_t Ps[64 * 8];   // closure partials, Ps[j*8 + w]
     __shared__ int32_t hrow[64], hcol[64];
     __shared__ uint8_t ca[64], cb[64];
+    __shared__ unsigned long long GM[8];  // GM[g] bit i: pairing of (row i, column 8g)
 
     const TileWork it = items[blockIdx.x];
     const FoldDesc& f = it.f;
     const int A = it.A, d = it.d, B = A + d;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int j = tid & 63;
-    const int r0 = wave * RPW;
+    const int lane = tid & 63;
+    const int g = lane >> 3, c = lane & 7;
+    const int j = wave * 8 + c;  // this lane's column
+    const int r0 = g * 8;        // first of this lane's 8 rows
     const long long ld = f.ld;
     const int aT = A * T, bT = B * T;
     const int16_t* F = f.F;
@@ -252,20 +268,20 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
         const int ip = e >> 6, i = e & 63;  // row ip of L, read coalesced
         lv[u] = (ip < i && i < T) ? (int)F[(aT + ip) * ld + aT + i] : kNeg;
     }
-    int ureg[8];  // U(8w + c, j); -inf where the split point is not left of column j
+    int ureg[8];  // U(8g + t, j); -inf where the split point is not left of column j
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int jp = r0 + c;
-        ureg[c] = (jp <= j && j < T) ? (int)F[(bT + jp) * ld + bT + j] : kNeg;
+    for (int t = 0; t < 8; ++t) {
+        const int jp = r0 + t;
+        ureg[t] = (jp <= j && j < T) ? (int)F[(bT + jp) * ld + bT + j] : kNeg;
     }
-    int acc[RPW];
+    int acc[8];
     int32_t* accp = it.acc + r0 * 64 + j;
     if (it.nslot > 0) {
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) acc[r] = accp[r * 64];
+        for (int r = 0; r < 8; ++r) acc[r] = accp[r * 64];
     } else {
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) acc[r] = 0;
+        for (int r = 0; r < 8; ++r) acc[r] = 0;
     }
     if constexpr (RSZ >= 16) {
         for (int x = tid * 16; x < RSZ; x += kTileThreads * 16)
@@ -274,15 +290,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
         if (tid < RSZ) Rl[tid] = Rg[tid];
     }
     if constexpr (kStageEdges) {
-        // edge e: C = A+1 (e = 0) and C = B-1 (e = 1); row words of (A, C), column words of (C, B)
-        for (int x = tid; x < nedge * 2 * G * 16; x += kTileThreads) {
-            const int e = x / (2 * G * 16), rem = x % (2 * G * 16);
-            const int rc = rem / (G * 16), o = rem % (G * 16);
+        // edge e: C = A+1 (e = 0) and C = B-1 (e = 1); row block of (A, C)
+        // (bases, bits) then column block of (C, B)
+        for (int x = tid; x < nedge * 3 * G * 16; x += kTileThreads) {
+            const int e = x / (3 * G * 16), o = x % (3 * G * 16);
             const int C = e == 0 ? A + 1 : B - 1;
-            const uint32_t* src = rc == 0 ? f.RS + tile_index(f.NT, A, C - A) * SW
-                                          : f.CS + tile_index(f.NT, C, B - C) * SW;
-            *reinterpret_cast<uint4*>(&EW[(e * 2 + rc) * G * 64 + o * 4]) =
-                *reinterpret_cast<const uint4*>(src + o * 4);
+            const uint32_t* src = o < 2 * G * 16 ? f.RS + tile_index(f.NT, A, C - A) * RW + o * 4
+                                                 : f.CS + tile_index(f.NT, C, B - C) * SW + (o - 2 * G * 16) * 4;
+            *reinterpret_cast<uint4*>(&EW[e * 3 * G * 64 + o * 4]) = *reinterpret_cast<const uint4*>(src);
         }
     }
     if (tid < 64) {
@@ -302,7 +317,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
     }
     if (it.nslot > 0) {  // hand the accumulator back zeroed for its next use
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) accp[r * 64] = 0;
+        for (int r = 0; r < 8; ++r) accp[r * 64] = 0;
     }
     __syncthreads();
 
@@ -326,34 +341,57 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
     // ---- groups of the two end tiles C = A+1 and C = B-1
     if constexpr (kStageEdges) {
         for (int e = 0; e < nedge; ++e) {
-            const uint32_t* er = &EW[(e * 2 + 0) * G * 64];
-            const uint32_t* ec = &EW[(e * 2 + 1) * G * 64];
+            const uint32_t* eb = &EW[e * 3 * G * 64];
+            const uint32_t* eh = eb + G * 64;
+            const uint32_t* ec = eh + G * 64;
 #pragma unroll 2
             for (int k = 0; k < G; ++k) {
                 const uint32_t cw = ec[k * 64 + j];
-                const uint4 ra = *reinterpret_cast<const uint4*>(&er[k * 64 + r0]);
-                const uint4 rb = *reinterpret_cast<const uint4*>(&er[k * 64 + r0 + 4]);
-                acc[0] = max(acc[0], rlookup<Q>(Rl, ra.x, cw));
-                acc[1] = max(acc[1], rlookup<Q>(Rl, ra.y, cw));
-                acc[2] = max(acc[2], rlookup<Q>(Rl, ra.z, cw));
-                acc[3] = max(acc[3], rlookup<Q>(Rl, ra.w, cw));
-                acc[4] = max(acc[4], rlookup<Q>(Rl, rb.x, cw));
-                acc[5] = max(acc[5], rlookup<Q>(Rl, rb.y, cw));
-                acc[6] = max(acc[6], rlookup<Q>(Rl, rb.z, cw));
-                acc[7] = max(acc[7], rlookup<Q>(Rl, rb.w, cw));
+                const uint32_t clo = cw & 0xffffu;
+                const int chi = (int)(cw >> 16);
+                const uint4 ba = *reinterpret_cast<const uint4*>(&eb[k * 64 + r0]);
+                const uint4 bb = *reinterpret_cast<const uint4*>(&eb[k * 64 + r0 + 4]);
+                const uint4 ha = *reinterpret_cast<const uint4*>(&eh[k * 64 + r0]);
+                const uint4 hb = *reinterpret_cast<const uint4*>(&eh[k * 64 + r0 + 4]);
+                const uint32_t bs[8] = {ba.x, ba.y, ba.z, ba.w, bb.x, bb.y, bb.z, bb.w};
+                const uint32_t hs[8] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w};
+#pragma unroll
+                for (int r = 0; r < 8; ++r) acc[r] = max(acc[r], (int)bs[r] + chi + (int)Rl[hs[r] + clo]);
             }
         }
     } else {
-        if (d >= 2) between_accumulate<Q, RPW>(acc, Rl, f.RS, f.CS, f.NT, A, B, A + 1, A + 2, r0, j);
-        if (d >= 3) between_accumulate<Q, RPW>(acc, Rl, f.RS, f.CS, f.NT, A, B, B - 1, B, r0, j);
+        // rows r0..r0+7 of column j: the wave-uniform row-word path needs all
+        // lanes on the same rows, so go element by element through LDS-free
+        // global reads (q < 4 only)
+        for (int e = 0; e < nedge; ++e) {
+            const int C = e == 0 ? A + 1 : B - 1;
+            const uint32_t* rb = f.RS + tile_index(f.NT, A, C - A) * RW;
+            const uint32_t* cs = f.CS + tile_index(f.NT, C, B - C) * SW;
+            for (int k = 0; k < G; ++k) {
+                const uint32_t cw = cs[k * 64 + j];
+                const uint32_t clo = cw & 0xffffu;
+                const int chi = (int)(cw >> 16);
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    acc[r] = max(acc[r], (int)rb[k * 64 + r0 + r] + chi + (int)Rl[rb[G * 64 + k * 64 + r0 + r] + clo]);
+            }
+        }
     }
 
     // pairing bits of this lane's rows; pairing terms whose partner lies
     // outside the tile (last row, first column) come from the halo
     const int cbj = cb[j];
     uint32_t pmask = 0;
+    if (wave == 0) {  // pairing masks of the slice-start columns, by ballot over rows
+        const int cal = ca[lane];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
+        for (int gg = 0; gg < 8; ++gg) {
+            const unsigned long long m = __ballot(cal + (int)cb[gg * 8] == 3);
+            if (lane == 0) GM[gg] = m;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
         const int i = r0 + r;
         if (i < T && j < T) {
             const int bp = (ca[i] + cbj == 3) ? 1 : 0;
@@ -365,103 +403,81 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
 
     // ---- rows bottom-up.  Rows >= T (only when T < 64) are inert: their
     // pushes are -inf in Lt and their pairing into row T-1 is skipped.
-    if (wave == 7) Qs[1][j] = acc[7];  // row 63 has no row below it
+    if (g == 7) Qs[1][j] = acc[7];  // row 63: Q complete (no row below)
     __syncthreads();
-    const int jl = j > 0 ? j - 1 : 0;
+    const unsigned long long gmask = GM[g];
 
 #pragma unroll 1
     for (int blk = 7; blk >= 0; --blk) {
 #pragma unroll
         for (int rr = 7; rr >= 0; --rr) {
             const int i = blk * 8 + rr;
-            {   // closure partial over j' in [8w, 8w+8)
-                const int4 qa = *reinterpret_cast<const int4*>(&Qs[i & 1][r0]);
-                const int4 qb = *reinterpret_cast<const int4*>(&Qs[i & 1][r0 + 4]);
-                int p = max(max(qa.x + ureg[0], qa.y + ureg[1]), max(qa.z + ureg[2], qa.w + ureg[3]));
-                p = max(p, max(max(qb.x + ureg[4], qb.y + ureg[5]), max(qb.z + ureg[6], qb.w + ureg[7])));
-                Ps[j * 8 + wave] = p;
+            // Q(i, 8g..8g+7); the pairing term of column 8g is added here
+            const int4 qa = *reinterpret_cast<const int4*>(&Qs[i & 1][r0]);
+            const int4 qb = *reinterpret_cast<const int4*>(&Qs[i & 1][r0 + 4]);
+            const int4 la = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0]);
+            const int4 lb = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0 + 4]);
+            int q0 = qa.x;
+            if (i < T - 1 && g > 0) {
+                const int xl = Xs[(i + 1) * 64 + r0 - 1];  // X(i+1, 8g-1)
+                q0 = max(q0, (int)((gmask >> i) & 1u) + xl);
             }
-            __syncthreads();
+            // closure over j' in [8g, 8g+8), then across the 8 lane groups
+            int p = max(max(q0 + ureg[0], qa.y + ureg[1]), max(qa.z + ureg[2], qa.w + ureg[3]));
+            p = max(p, max(max(qb.x + ureg[4], qb.y + ureg[5]), max(qb.z + ureg[6], qb.w + ureg[7])));
+            const int xi = max_over_groups(p);  // X(i, j)
+            if (g == 0) Xs[i * 64 + j] = xi;
+            // pushes: rows of this block above i, one split at a time (rows
+            // of other lanes' blocks above get the same exact terms, harmless)
+            {
+                const int lt[8] = {la.x, la.y, la.z, la.w, lb.x, lb.y, lb.z, lb.w};
+                if constexpr (kBlockFR) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r)
+                        if (r < rr) acc[r] = max(acc[r], lt[r] + xi);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) acc[r] = max(acc[r], lt[r] + xi);
+                }
+            }
             if constexpr (kBlockFR) {
-                if (wave == blk) {
-                    // issue every read of this phase before the first wait
-                    const int4 pa = *reinterpret_cast<const int4*>(&Ps[j * 8]);
-                    const int4 pb = *reinterpret_cast<const int4*>(&Ps[j * 8 + 4]);
-                    int4 pla, plb, la, lb;
-                    if (rr > 0) {
-                        pla = *reinterpret_cast<const int4*>(&Ps[jl * 8]);
-                        plb = *reinterpret_cast<const int4*>(&Ps[jl * 8 + 4]);
-                        la = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0]);
-                        lb = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0 + 4]);
-                    }
-                    const int xi = max8(pa, pb);
-                    Xs[i * 64 + j] = xi;
-                    if (rr > 0) {
-                        const int left = max8(pla, plb);
-                        const int lt[8] = {la.x, la.y, la.z, la.w, lb.x, lb.y, lb.z, lb.w};
+                if (rr == 0 && blk > 0 && g < blk) {
+                    // block blk finished: its q-groups into every row above it
 #pragma unroll
-                        for (int r = 0; r < 8; ++r)
-                            if (r < rr) acc[r] = max(acc[r], lt[r] + xi);
-                        int qv = acc[rr - 1];
-                        if (i < T && j > 0) qv = max(qv, (int)((pmask >> (rr - 1)) & 1u) + left);
-                        Qs[(i - 1) & 1][j] = qv;
+                    for (int gg = 0; gg < GPB; ++gg) {
+                        const int k = blk * GPB + gg;
+                        const int top = k * Q;
+                        // column word of group k at column j from rows top..top+q-1
+                        int xs[Q];
+#pragma unroll
+                        for (int p2 = 0; p2 < Q; ++p2) xs[p2] = (top + p2 == i) ? xi : Xs[(top + p2) * 64 + j];
+                        uint32_t cbits = 0;
+#pragma unroll
+                        for (int p2 = 1; p2 <= M; ++p2) cbits |= (uint32_t)(xs[p2 - 1] > xs[p2]) << (p2 - 1);
+                        const uint32_t cw = ((uint32_t)xs[0] << 16) | cbits;
+                        const uint4 wa = *reinterpret_cast<const uint4*>(&LW[k * 64 + r0]);
+                        const uint4 wb = *reinterpret_cast<const uint4*>(&LW[k * 64 + r0 + 4]);
+                        acc[0] = max(acc[0], rlookup<Q>(Rl, wa.x, cw));
+                        acc[1] = max(acc[1], rlookup<Q>(Rl, wa.y, cw));
+                        acc[2] = max(acc[2], rlookup<Q>(Rl, wa.z, cw));
+                        acc[3] = max(acc[3], rlookup<Q>(Rl, wa.w, cw));
+                        acc[4] = max(acc[4], rlookup<Q>(Rl, wb.x, cw));
+                        acc[5] = max(acc[5], rlookup<Q>(Rl, wb.y, cw));
+                        acc[6] = max(acc[6], rlookup<Q>(Rl, wb.z, cw));
+                        acc[7] = max(acc[7], rlookup<Q>(Rl, wb.w, cw));
                     }
                 }
-                if (rr == 0 && blk > 0) {
-                    __syncthreads();  // the block's rows are in Xs
-                    if (wave < blk) {
-#pragma unroll
-                        for (int g = 0; g < GPB; ++g) {
-                            const int k = blk * GPB + g;
-                            const int top = k * Q;
-                            uint32_t c = 0;
-#pragma unroll
-                            for (int p = 1; p <= M; ++p)
-                                c |= (uint32_t)(Xs[(top + p - 1) * 64 + j] > Xs[(top + p) * 64 + j]) << (p - 1);
-                            const uint32_t cw = ((uint32_t)Xs[top * 64 + j] << 16) | c;
-                            const uint4 wa = *reinterpret_cast<const uint4*>(&LW[k * 64 + r0]);
-                            const uint4 wb = *reinterpret_cast<const uint4*>(&LW[k * 64 + r0 + 4]);
-                            acc[0] = max(acc[0], rlookup<Q>(Rl, wa.x, cw));
-                            acc[1] = max(acc[1], rlookup<Q>(Rl, wa.y, cw));
-                            acc[2] = max(acc[2], rlookup<Q>(Rl, wa.z, cw));
-                            acc[3] = max(acc[3], rlookup<Q>(Rl, wa.w, cw));
-                            acc[4] = max(acc[4], rlookup<Q>(Rl, wb.x, cw));
-                            acc[5] = max(acc[5], rlookup<Q>(Rl, wb.y, cw));
-                            acc[6] = max(acc[6], rlookup<Q>(Rl, wb.z, cw));
-                            acc[7] = max(acc[7], rlookup<Q>(Rl, wb.w, cw));
-                        }
-                        if (wave == blk - 1) {
-                            const int left = Xs[i * 64 + jl];
-                            int qv = acc[7];
-                            if (i < T && j > 0) qv = max(qv, (int)((pmask >> 7) & 1u) + left);
-                            Qs[(i - 1) & 1][j] = qv;
-                        }
-                    }
-                }
-            } else {
-                const int xi = max8(*reinterpret_cast<const int4*>(&Ps[j * 8]),
-                                    *reinterpret_cast<const int4*>(&Ps[j * 8 + 4]));
-                const int left = max8(*reinterpret_cast<const int4*>(&Ps[jl * 8]),
-                                      *reinterpret_cast<const int4*>(&Ps[jl * 8 + 4]));
-                if (wave == blk) Xs[i * 64 + j] = xi;
-                const int4 la = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0]);
-                const int4 lb = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0 + 4]);
-                acc[0] = max(acc[0], la.x + xi);
-                acc[1] = max(acc[1], la.y + xi);
-                acc[2] = max(acc[2], la.z + xi);
-                acc[3] = max(acc[3], la.w + xi);
-                acc[4] = max(acc[4], lb.x + xi);
-                acc[5] = max(acc[5], lb.y + xi);
-                acc[6] = max(acc[6], lb.z + xi);
-                acc[7] = max(acc[7], lb.w + xi);
-                if (i >= 1) {
-                    const int owner = (rr > 0) ? blk : blk - 1;
-                    const int slot = (rr > 0) ? rr - 1 : 7;
-                    if (wave == owner) {
-                        int qv = acc[slot];
-                        if (i < T && j > 0) qv = max(qv, (int)((pmask >> slot) & 1u) + left);
-                        Qs[(i - 1) & 1][j] = qv;
-                    }
+            }
+            // Q of row i-1 for this lane's column (pairing partner X(i, j-1)
+            // is the lane to the left; column 8w gets it from its readers)
+            if (i >= 1) {
+                const int left = __builtin_amdgcn_update_dpp(kNeg, xi, 0x111, 0xF, 0xF, false);  // row_shr:1
+                const int gq = (rr > 0) ? blk : blk - 1;
+                const int slot = (rr > 0) ? rr - 1 : 7;
+                if (g == gq) {
+                    int qv = acc[slot];
+                    if (i < T && c > 0) qv = max(qv, (int)((pmask >> slot) & 1u) + left);
+                    Qs[(i - 1) & 1][j] = qv;
                 }
             }
             __syncthreads();
@@ -471,20 +487,24 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
     // ---- emit: dense cells, row words (ballot), column words
     int16_t* Fw = f.F;
     const long long t_idx = tile_index(f.NT, A, d);
-    uint32_t* RSw = f.RS + t_idx * SW;
+    uint32_t* RSw = f.RS + t_idx * RW;  // bases, then bits at + G*64
     uint32_t* CSw = f.CS + t_idx * SW;
+    {
+        const int wv = tid >> 6, ln = tid & 63;  // row-major view: wave -> 8 rows, lane -> column
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-        const int i = r0 + r;
-        if (i < T) {
-            const int v = Xs[i * 64 + j];
-            if (j < T) Fw[(aT + i) * ld + bT + j] = (int16_t)v;
-            const int left = __shfl_up(v, 1);
-            const unsigned long long diff = __ballot(j > 0 && j < T && v > left);
-            if (j < T && (j % Q) == 0) {
-                uint32_t h = 0;
-                if constexpr (M > 0) h = (uint32_t)(diff >> (j + 1)) & ((1u << M) - 1u);
-                RSw[(j / Q) * 64 + i] = ((uint32_t)v << 16) | (h << M);
+        for (int r = 0; r < 8; ++r) {
+            const int i = wv * 8 + r;
+            if (i < T) {
+                const int v = Xs[i * 64 + ln];
+                if (ln < T) Fw[(aT + i) * ld + bT + ln] = (int16_t)v;
+                const int lft = __shfl_up(v, 1);
+                const unsigned long long diff = __ballot(ln > 0 && ln < T && v > lft);
+                if (ln < T && (ln % Q) == 0) {
+                    uint32_t h = 0;
+                    if constexpr (M > 0) h = (uint32_t)(diff >> (ln + 1)) & ((1u << M) - 1u);
+                    RSw[(ln / Q) * 64 + i] = (uint32_t)v;
+                    RSw[G * 64 + (ln / Q) * 64 + i] = h << M;
+                }
             }
         }
     }
@@ -492,11 +512,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
         const int k = e >> 6, jj = e & 63;
         if (jj < T) {
             const int top = k * Q;
-            uint32_t c = 0;
+            uint32_t cbits = 0;
 #pragma unroll
             for (int p = 1; p <= M; ++p)
-                c |= (uint32_t)(Xs[(top + p - 1) * 64 + jj] > Xs[(top + p) * 64 + jj]) << (p - 1);
-            CSw[k * 64 + jj] = ((uint32_t)Xs[top * 64 + jj] << 16) | c;
+                cbits |= (uint32_t)(Xs[(top + p - 1) * 64 + jj] > Xs[(top + p) * 64 + jj]) << (p - 1);
+            CSw[k * 64 + jj] = ((uint32_t)Xs[top * 64 + jj] << 16) | cbits;
         }
     }
 }

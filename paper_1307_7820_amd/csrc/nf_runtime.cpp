@@ -153,8 +153,9 @@ Geom make_geom(int n, int q)
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     g.codes_bytes = up((size_t)g.NT * T + 64);
     g.F_bytes = up((size_t)g.ld * g.ld * sizeof(int16_t));
-    g.state_bytes = up((size_t)tile_count(g.NT) * state_words(q) * sizeof(uint32_t));
-    g.bytes = g.codes_bytes + g.F_bytes + 2 * g.state_bytes;
+    g.rs_bytes = up((size_t)tile_count(g.NT) * row_words(q) * sizeof(uint32_t));
+    g.cs_bytes = up((size_t)tile_count(g.NT) * state_words(q) * sizeof(uint32_t));
+    g.bytes = g.codes_bytes + g.F_bytes + g.rs_bytes + g.cs_bytes;
     return g;
 }
 
@@ -325,7 +326,7 @@ int plan_allocate(Plan& p)
         fd[f].codes = (const uint8_t*)(base + off);
         fd[f].F = (int16_t*)(base + off + g.codes_bytes);
         fd[f].RS = (uint32_t*)(base + off + g.codes_bytes + g.F_bytes);
-        fd[f].CS = (uint32_t*)(base + off + g.codes_bytes + g.F_bytes + g.state_bytes);
+        fd[f].CS = (uint32_t*)(base + off + g.codes_bytes + g.F_bytes + g.rs_bytes);
         fd[f].n = g.n;
         fd[f].NT = g.NT;
         fd[f].ld = g.ld;

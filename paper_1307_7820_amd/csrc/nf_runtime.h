@@ -41,7 +41,7 @@ struct DevBuf {
 // Device layout of one fold (see nf_internal.h).
 struct Geom {
     int n = 0, NT = 0, ld = 0;
-    size_t codes_bytes = 0, F_bytes = 0, state_bytes = 0, bytes = 0;
+    size_t codes_bytes = 0, F_bytes = 0, rs_bytes = 0, cs_bytes = 0, bytes = 0;
     size_t codes_off = 0;  // offset of this fold's block in its arena
 };
 

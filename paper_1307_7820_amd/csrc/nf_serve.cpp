@@ -268,7 +268,7 @@ void admit(Engine& E, Device& D, std::vector<Active*>& active, std::vector<Activ
         a->fd.codes = (const uint8_t*)base;
         a->fd.F = (int16_t*)(base + g.codes_bytes);
         a->fd.RS = (uint32_t*)(base + g.codes_bytes + g.F_bytes);
-        a->fd.CS = (uint32_t*)(base + g.codes_bytes + g.F_bytes + g.state_bytes);
+        a->fd.CS = (uint32_t*)(base + g.codes_bytes + g.F_bytes + g.rs_bytes);
         a->fd.n = g.n;
         a->fd.NT = g.NT;
         a->fd.ld = g.ld;

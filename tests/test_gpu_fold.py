@@ -155,3 +155,13 @@ def test_errors(nf):
     assert e.value.code == nf.NF_E_INVAL
     with pytest.raises(nf.NFError):
         nf.nf_fold("ACGU", q=12)
+
+
+def test_autotune_picks_and_caches(nf):
+    q = nf.nf_autotune(1500, 4, 8, 1)
+    assert 4 <= q <= 8
+    assert nf.nf_autotune_q(1500) == q
+    # a fold with q = 0 uses the tuned value and still matches the oracle
+    s = gen.iid_sequence(1500, [111, 0])
+    score, T = nf.nf_fold(s, q=0, table=True)
+    assert np.array_equal(T, oracle.fold_table(s))
