@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: int32 VALU lane-ops/s
 OPS_PER_LOOKUP = 2.5                          # index add + 3-input add + half a 3-input max
+OPS_PER_TERM = 2.0                            # add + max of one Eq. 1 term
 PEAK_HBM = 8.0e12
 
 
@@ -64,27 +65,69 @@ def time_fold(nf, torch, seq: str, q: int, steps: int, warmup: int):
     return ms, wall, int(d_score.item()), codes
 
 
+WORKLOAD_NAMES = {6000: "n6000", 16000: "n16000"}
+
+
+def kernels_source_hash() -> str:
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1307_7820_amd", "csrc", "nf_kernels.hip")
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_bytes(kernel: str, q: int, n: int):
+    """HBM bytes per launch of `kernel`, from the committed rocprofv3 counter
+    summary profiles/<kernel>_q<q>_<workload>_pmc.txt: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch, separate runs), each scaled by what the same
+    counter reads for a plain device copy of known size.  None when there is
+    no summary for this kernel and workload, or when the kernel source has
+    changed since the counters were taken (its hash is in the summary)."""
+    wl = WORKLOAD_NAMES.get(n)
+    if wl is None:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "%s_q%d_%s_pmc.txt" % (kernel, q, wl))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic:"):
+                for kv in line.split()[1:]:
+                    key, _, v = kv.partition("=")
+                    vals[key] = v
+    try:
+        if vals.get("kernels_sha256") != kernels_source_hash():
+            return None
+        return 1024.0 * (float(vals["fetch_kib"]) * float(vals["fetch_scale"]) +
+                         float(vals["write_kib"]) * float(vals["write_scale"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def roofline(nf, codes, n, q, reps=3):
+    """Roofline of the kernel that takes most of the fill's device time.
+
+    Algorithmic work per launch = 2.5 VALU lane-ops per Eq. 3 lookup + 2 per
+    Eq. 1 term evaluated one by one inside a tile (add, max), both counted
+    from the work lists; duration = HIP events around each launch on the
+    launching stream."""
     prof = nf.nf_profile_fold(codes, n, q, reps)
-    k = max(range(3), key=lambda i: prof.ms[i])
+    ks = [i for i in range(4) if prof.launches[i] > 0]
+    k = max(ks, key=lambda i: prof.ms[i])
     name = nf.KERNEL_NAMES[k]
+    per_launch_s = prof.ms[k] / 1e3 / prof.launches[k]
+    ops = (OPS_PER_LOOKUP * prof.lookups[k] + OPS_PER_TERM * prof.splits[k]) / prof.launches[k]
+    ach = ops / per_launch_s / 1e12
+    peak = PEAK_VALU_LANE_OPS / 1e12
     out = {"kernel": name, "launches_per_fold": prof.launches[k] // reps,
-           "avg_launch_us": 1e3 * prof.ms[k] / max(1, prof.launches[k]),
-           "per_kernel_ms_per_fold": {nf.KERNEL_NAMES[i]: prof.ms[i] / reps for i in range(3)}}
-    if k in (1, 2) and prof.lookups[k] > 0:
-        ops = OPS_PER_LOOKUP * prof.lookups[k] / prof.launches[k]
-        t = prof.ms[k] / 1e3 / prof.launches[k]
-        ach = ops / t / 1e12
-        out.update({"bound": "alu", "achieved": ach, "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "TOP/s",
-                    "frac": ach / (PEAK_VALU_LANE_OPS / 1e12),
-                    "lookups_per_launch": prof.lookups[k] / prof.launches[k],
-                    "glookups_per_s": prof.lookups[k] / (prof.ms[k] / 1e3) / 1e9})
-    else:
-        out.update({"bound": "alu", "achieved": None, "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "TOP/s",
-                    "frac": None})
-    out["traffic"] = None
-    out["q"] = prof.q
-    out["tile"] = prof.tile
+           "avg_launch_us": 1e6 * per_launch_s,
+           "per_kernel_ms_per_fold": {nf.KERNEL_NAMES[i]: prof.ms[i] / reps for i in ks},
+           "bound": "alu", "achieved": ach, "peak": peak, "unit": "TOP/s", "frac": ach / peak,
+           "lookups_per_launch": prof.lookups[k] / prof.launches[k],
+           "terms_per_launch": prof.splits[k] / prof.launches[k],
+           "glookups_per_s": prof.lookups[k] / (prof.ms[k] / 1e3) / 1e9,
+           "traffic": traffic_bytes(name, q, n),
+           "q": prof.q, "tile": prof.tile}
     return out
 
 

@@ -39,17 +39,17 @@ __device__ __forceinline__ const NF_CONST T* as_const(const T* p)
 
 // Copy the q-dependent R table (RSZ bytes) into LDS.
 template <int RSZ>
-__device__ __forceinline__ void load_R(uint8_t* Rl, const uint8_t* __restrict__ Rg)
+__device__ __forceinline__ void load_R(uint8_t* Rl, const uint8_t* __restrict__ Rg, int nthr)
 {
     if constexpr (RSZ >= 16) {
-        for (int x = threadIdx.x * 16; x < RSZ; x += kThreads * 16)
+        for (int x = threadIdx.x * 16; x < RSZ; x += nthr * 16)
             *reinterpret_cast<uint4*>(Rl + x) = *reinterpret_cast<const uint4*>(Rg + x);
     } else {
         if (threadIdx.x < RSZ) Rl[threadIdx.x] = Rg[threadIdx.x];
     }
 }
 
-// Between-group maxima for the 16 rows r0..r0+15 (wave-uniform) and column j
+// Between-group maxima for the RPW rows r0..r0+RPW-1 (wave-uniform) and column j
 // (the lane) of tile (A, B), over the groups of tiles C in [c0, c1).
 // For group k of tile C the row word comes from tile (A, C) and the column
 // word from tile (C, B); Eq. 3 turns the q split points of the group into
@@ -105,30 +105,31 @@ __global__ void k_copy_codes(const uint8_t* __restrict__ src, int n, uint8_t* __
 
 // Main-diagonal tiles (A, A): every split point lies inside the tile, so the
 // tile is filled by its own diagonals t = b - a = 2..T-1 (Eq. 1 directly).
+struct DiagLds {
+    int32_t X[64 * 65];  // padded stride 65: rows of a column are in distinct banks
+    uint8_t ca[64], cb[64];
+};
+
 template <int Q>
-__global__ __launch_bounds__(kThreads) void k_diag(const TileWork* __restrict__ items)
+__device__ __forceinline__ void diag_body(const TileWork& it, DiagLds& s, int tid, int nthr)
 {
     constexpr int T = tile_size(Q);
-    constexpr int XS = 65;  // padded stride: rows of a column are in distinct banks
-    __shared__ int32_t X[64 * XS];
-    __shared__ uint8_t ca[64], cb[64];
-
-    const TileWork it = items[blockIdx.x];
+    constexpr int XS = 65;
+    int32_t* X = s.X;
     const FoldDesc& f = it.f;
     const int aT = it.A * T;
-    const int tid = threadIdx.x;
 
-    for (int e = tid; e < 64 * XS; e += kThreads) X[e] = 0;
+    for (int e = tid; e < 64 * XS; e += nthr) X[e] = 0;
     if (tid < 64) {
-        ca[tid] = f.codes[aT + tid];                        // S_{a+1} for a = aT + i
-        cb[tid] = (aT + tid - 1 >= 0) ? f.codes[aT + tid - 1] : 0;  // S_b for b = aT + j
+        s.ca[tid] = f.codes[aT + tid];                              // S_{a+1} for a = aT + i
+        s.cb[tid] = (aT + tid - 1 >= 0) ? f.codes[aT + tid - 1] : 0;  // S_b for b = aT + j
     }
     __syncthreads();
 
     for (int t = 2; t < T; ++t) {
-        for (int i = tid; i < T - t; i += kThreads) {
+        for (int i = tid; i < T - t; i += nthr) {
             const int j = i + t;
-            int v = (ca[i] + cb[j] == 3) + X[(i + 1) * XS + (j - 1)];
+            int v = (s.ca[i] + s.cb[j] == 3) + X[(i + 1) * XS + (j - 1)];
             for (int m = i + 1; m < j; ++m) v = max(v, X[i * XS + m] + X[m * XS + j]);
             X[i * XS + j] = v;
         }
@@ -137,9 +138,38 @@ __global__ __launch_bounds__(kThreads) void k_diag(const TileWork* __restrict__ 
 
     int16_t* F = f.F;
     const long long ld = f.ld;
-    for (int e = tid; e < 64 * 64; e += kThreads) {
+    for (int e = tid; e < 64 * 64; e += nthr) {
         const int i = e >> 6, j = e & 63;
         if (i < T && j < T) F[(aT + i) * ld + aT + j] = (int16_t)X[i * XS + j];
+    }
+}
+
+template <int Q>
+__global__ __launch_bounds__(kThreads) void k_diag(const TileWork* __restrict__ items)
+{
+    __shared__ DiagLds s;
+    diag_body<Q>(items[blockIdx.x], s, threadIdx.x, kThreads);
+}
+
+// One between item: rows r0 = wave * RPW .. +RPW-1 and column j (the lane)
+// of the tile's 64x64 maxima, written to its accumulator.
+template <int Q, int RPW>
+__device__ __forceinline__ void between_body(const BetweenWork& it, const uint8_t* Rl,
+                                             const uint32_t* RS, const uint32_t* CS, int wave, int j)
+{
+    const int r0 = wave * RPW;
+    int acc[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) acc[r] = 0;
+    between_accumulate<Q, RPW>(acc, Rl, RS, CS, it.f.NT, it.A, it.A + it.d, it.c0, it.c1, r0, j);
+
+    int32_t* out = it.acc + r0 * 64 + j;
+    if (it.atomic) {  // several items share the tile's accumulator
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) atomicMax(out + r * 64, acc[r]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) out[r * 64] = acc[r];
     }
 }
 
@@ -147,31 +177,14 @@ template <int Q>
 __global__ __launch_bounds__(kThreads) void k_between(const BetweenWork* __restrict__ items,
                                                       const uint8_t* __restrict__ Rg)
 {
-    constexpr int M = Q - 1;
-    constexpr int RSZ = 1 << (2 * M);
+    constexpr int RSZ = 1 << (2 * (Q - 1));
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
 
-    const BetweenWork it = items[blockIdx.x];
-    const FoldDesc& f = it.f;
-    load_R<RSZ>(Rl, Rg);
+    const BetweenWork& it = items[blockIdx.x];
+    load_R<RSZ>(Rl, Rg, kThreads);
     __syncthreads();
-
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int j = threadIdx.x & 63;
-    const int r0 = wave * kRowsPerWave;
-    int acc[kRowsPerWave];
-#pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r) acc[r] = 0;
-    between_accumulate<Q, kRowsPerWave>(acc, Rl, f.RS, f.CS, f.NT, it.A, it.A + it.d, it.c0, it.c1, r0, j);
-
-    int32_t* out = it.acc + r0 * 64 + j;
-    if (it.atomic) {  // several items share the tile's accumulator
-#pragma unroll
-        for (int r = 0; r < kRowsPerWave; ++r) atomicMax(out + r * 64, acc[r]);
-    } else {
-#pragma unroll
-        for (int r = 0; r < kRowsPerWave; ++r) out[r * 64] = acc[r];
-    }
+    between_body<Q, kRowsPerWave>(it, Rl, it.f.RS, it.f.CS, wave, threadIdx.x & 63);
 }
 
 // Finish of an off-diagonal tile (A, B), B > A, by 8 wavefronts (512 threads).
@@ -224,29 +237,47 @@ __device__ __forceinline__ int max_over_groups(int v)
 }
 
 template <int Q>
-__global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restrict__ items,
-                                                       const uint8_t* __restrict__ Rg)
+struct TileLds {
+    static constexpr int G = groups_per_tile(Q);
+    static constexpr bool kBlockFR = (8 % Q) == 0;  // q-groups tile the 8-row blocks
+    static constexpr bool kStageEdges = G <= 16;    // end-tile words fit in LDS
+    int32_t Xs[64 * 64];  // finished cells, row-major
+    int32_t Lt[64 * 64];  // Lt[i*64 + i''] = L(i'', i) for i'' < i < T, else -inf
+    uint32_t LW[kBlockFR ? G * 64 : 4];        // row words of tile (A, A), [k][row]
+    uint32_t EW[kStageEdges ? 6 * G * 64 : 4];  // [edge][base|bits|col][k][64]
+    int32_t Qs[2][64];    // Q of the row being closed (double-buffered)
+    int32_t hrow[64], hcol[64];
+    uint8_t ca[64], cb[64];
+    unsigned long long GM[8];  // GM[g] bit i: pairing of (row i, column 8g)
+};
+
+// The finish of one tile by kTileThreads threads.  wait_pre() runs before
+// the loads that need the main-diagonal tiles (A, A) and (B, B); wait_main()
+// before the loads that need the tiles of diagonal d-1 and the between-group
+// maxima.  Both are collective (every thread calls them).
+template <int Q, class Pre, class Main>
+__device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl, TileLds<Q>& s, Pre&& wait_pre,
+                                          Main&& wait_main)
 {
     constexpr int M = Q - 1;
     constexpr int G = groups_per_tile(Q);
     constexpr int T = tile_size(Q);
-    constexpr int RSZ = 1 << (2 * M);
     constexpr int SW = state_words(Q);
     constexpr int RW = row_words(Q);
-    constexpr bool kBlockFR = (8 % Q) == 0;     // q-groups tile the 8-row blocks
+    constexpr bool kBlockFR = TileLds<Q>::kBlockFR;
     constexpr int GPB = kBlockFR ? 8 / Q : 1;   // groups per block
-    constexpr bool kStageEdges = G <= 16;       // end-tile words fit in LDS
-    __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
-    __shared__ __align__(16) int32_t Xs[64 * 64];  // finished cells, row-major
-    __shared__ __align__(16) int32_t Lt[64 * 64];  // Lt[i*64 + i''] = L(i'', i) for i'' < i < T, else -inf
-    __shared__ __align__(16) uint32_t LW[kBlockFR ? G * 64 : 4];  // row words of tile (A, A), [k][row]
-    __shared__ __align__(16) uint32_t EW[kStageEdges ? 6 * G * 64 : 4];  // [edge][base|bits|col][k][64]
-    __shared__ __align__(16) int32_t Qs[2][64];    // Q of the row being closed (double-buffered)
-    __shared__ int32_t hrow[64], hcol[64];
-    __shared__ uint8_t ca[64], cb[64];
-    __shared__ unsigned long long GM[8];  // GM[g] bit i: pairing of (row i, column 8g)
+    constexpr bool kStageEdges = TileLds<Q>::kStageEdges;
+    int32_t* Xs = s.Xs;
+    int32_t* Lt = s.Lt;
+    uint32_t* LW = s.LW;
+    uint32_t* EW = s.EW;
+    int32_t (*Qs)[64] = s.Qs;
+    int32_t* hrow = s.hrow;
+    int32_t* hcol = s.hcol;
+    uint8_t* ca = s.ca;
+    uint8_t* cb = s.cb;
+    unsigned long long* GM = s.GM;
 
-    const TileWork it = items[blockIdx.x];
     const FoldDesc& f = it.f;
     const int A = it.A, d = it.d, B = A + d;
     const int tid = threadIdx.x;
@@ -260,7 +291,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
     const int16_t* F = f.F;
     const int nedge = d >= 3 ? 2 : (d == 2 ? 1 : 0);
 
-    // ---- prologue: every load issued before the first wait
+    // ---- prologue, part 1: L, U and the codes
+    wait_pre();
     int lv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -274,6 +306,13 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
         const int jp = r0 + t;
         ureg[t] = (jp <= j && j < T) ? (int)F[(bT + jp) * ld + bT + j] : kNeg;
     }
+    if (tid < 64) {
+        ca[tid] = f.codes[aT + tid];      // S_{a+1}, a = AT + i
+        cb[tid] = f.codes[bT + tid - 1];  // S_b,     b = BT + j  (BT >= 1)
+    }
+
+    // ---- prologue, part 2: the between maxima, the end tiles and the halo
+    wait_main();
     int acc[8];
     int32_t* accp = it.acc + r0 * 64 + j;
     if (it.nslot > 0) {
@@ -282,12 +321,6 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
     } else {
 #pragma unroll
         for (int r = 0; r < 8; ++r) acc[r] = 0;
-    }
-    if constexpr (RSZ >= 16) {
-        for (int x = tid * 16; x < RSZ; x += kTileThreads * 16)
-            *reinterpret_cast<uint4*>(Rl + x) = *reinterpret_cast<const uint4*>(Rg + x);
-    } else {
-        if (tid < RSZ) Rl[tid] = Rg[tid];
     }
     if constexpr (kStageEdges) {
         // edge e: C = A+1 (e = 0) and C = B-1 (e = 1); row block of (A, C)
@@ -300,15 +333,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
             *reinterpret_cast<uint4*>(&EW[e * 3 * G * 64 + o * 4]) = *reinterpret_cast<const uint4*>(src);
         }
     }
-    if (tid < 64) {
-        if (tid < T) {
-            const int hr_r = aT + T, hr_c = bT - 1 + tid;  // F((A+1)T, BT-1+j)
-            hrow[tid] = hr_c >= hr_r ? F[hr_r * ld + hr_c] : 0;
-            const int hc_r = aT + 1 + tid, hc_c = bT - 1;  // F(AT+1+i, BT-1)
-            hcol[tid] = hc_c >= hc_r ? F[hc_r * ld + hc_c] : 0;
-        }
-        ca[tid] = f.codes[aT + tid];      // S_{a+1}, a = AT + i
-        cb[tid] = f.codes[bT + tid - 1];  // S_b,     b = BT + j  (BT >= 1)
+    if (tid < T) {
+        const int hr_r = aT + T, hr_c = bT - 1 + tid;  // F((A+1)T, BT-1+j)
+        hrow[tid] = hr_c >= hr_r ? F[hr_r * ld + hr_c] : 0;
+        const int hc_r = aT + 1 + tid, hc_c = bT - 1;  // F(AT+1+i, BT-1)
+        hcol[tid] = hc_c >= hc_r ? F[hc_r * ld + hc_c] : 0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -505,6 +534,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
                     RSw[(ln / Q) * 64 + i] = (uint32_t)v;
                     RSw[G * 64 + (ln / Q) * 64 + i] = h << M;
                 }
+            } else if (ln < G) {
+                // padding row (T < 64): readers load whole 64-row lines, so
+                // give it words that keep their sums bounded and R in range
+                RSw[ln * 64 + i] = 0;
+                RSw[G * 64 + ln * 64 + i] = 0;
             }
         }
     }
@@ -517,14 +551,180 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
             for (int p = 1; p <= M; ++p)
                 cbits |= (uint32_t)(Xs[(top + p - 1) * 64 + jj] > Xs[(top + p) * 64 + jj]) << (p - 1);
             CSw[k * 64 + jj] = ((uint32_t)Xs[top * 64 + jj] << 16) | cbits;
+        } else {
+            CSw[k * 64 + jj] = 0;  // padding column, as for padding rows
         }
     }
 }
 
-__global__ void k_scores(const FoldDesc* __restrict__ folds, int nfolds, int32_t* __restrict__ scores)
+template <int Q>
+__global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restrict__ items,
+                                                       const uint8_t* __restrict__ Rg)
+{
+    constexpr int RSZ = 1 << (2 * (Q - 1));
+    __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
+    __shared__ __align__(16) TileLds<Q> s;
+    load_R<RSZ>(Rl, Rg, kTileThreads);  // read after the first barrier of the body
+    tile_body<Q>(items[blockIdx.x], Rl, s, [] {}, [] {});
+}
+
+// One wavefront step in one launch: workgroups [0, ntile) finish the tiles
+// of diagonal s, the rest run the between chunks of diagonal s+1 (which only
+// read diagonals <= s-1 and write the other half of the accumulators).
+template <int Q>
+__global__ __launch_bounds__(kTileThreads) void k_stage(const TileWork* __restrict__ titems, int ntile,
+                                                        const BetweenWork* __restrict__ bitems,
+                                                        const uint8_t* __restrict__ Rg)
+{
+    constexpr int RSZ = 1 << (2 * (Q - 1));
+    constexpr int kRows = 64 / (kTileThreads / 64);
+    __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
+    __shared__ __align__(16) TileLds<Q> s;
+    load_R<RSZ>(Rl, Rg, kTileThreads);  // read after the first barrier of either body
+    const int b = blockIdx.x;
+    if (b < ntile) {
+        tile_body<Q>(titems[b], Rl, s, [] {}, [] {});
+    } else {
+        __syncthreads();
+        const BetweenWork& it = bitems[b - ntile];
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        between_body<Q, kRows>(it, Rl, it.f.RS, it.f.CS, wave, threadIdx.x & 63);
+    }
+}
+
+// ---- persistent fill
+
+// Dependency waits of the persistent fill.  One thread polls the counters
+// (agent-scope atomic loads) until every one reaches its target, then an
+// agent-scope acquire makes the producers' data visible to the workgroup;
+// the barrier releases the other threads.  The wait gives up after
+// kWaitTicks of the 100 MHz constant clock, or as soon as any workgroup has
+// given up, and flags err: every wave always gets past it.
+constexpr long long kWaitTicks = 400000000;  // 4 s
+constexpr int kQueueRowsPerWave = 64 / (kTileThreads / 64);  // between rows per wave
+
+__device__ __forceinline__ int ld_agent(const int32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void wait_ge(const int32_t* p0, int v0, const int32_t* p1, int v1, const int32_t* p2,
+                                        int v2, int32_t* err)
+{
+    if (threadIdx.x == 0) {
+        const long long t0 = (long long)wall_clock64();
+        for (;;) {
+            const bool ok = (!p0 || ld_agent(p0) >= v0) && (!p1 || ld_agent(p1) >= v1) && (!p2 || ld_agent(p2) >= v2);
+            if (ok || ld_agent(err) != 0) break;
+            if ((long long)wall_clock64() - t0 > kWaitTicks) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// Publish the workgroup's results: every wave waits for its own stores and
+// atomics to complete, then one thread writes the L2 back to memory
+// (agent-scope release) and bumps the counter.
+__device__ __forceinline__ void signal_add(int32_t* p)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <int Q>
+union QueueLds {
+    TileLds<Q> t;
+    DiagLds dg;
+};
+
+template <int Q>
+__global__ __launch_bounds__(kTileThreads, 4) void k_queue(const QItem* __restrict__ items, int nitems,
+                                                        const QFold* __restrict__ folds,
+                                                        const uint8_t* __restrict__ Rg, int32_t* head, int32_t* err)
+{
+    constexpr int RSZ = 1 << (2 * (Q - 1));
+    __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
+    __shared__ __align__(16) QueueLds<Q> u;
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    load_R<RSZ>(Rl, Rg, kTileThreads);  // read after the first barrier below
+
+    for (;;) {
+        __syncthreads();  // every wave is done with the previous item's LDS
+        if (tid == 0) s_item = atomicAdd(head, 1);
+        __syncthreads();
+        const int k = __builtin_amdgcn_readfirstlane(s_item);
+        if (k >= nitems) break;
+        const QItem& qi = items[k];
+        const QFold& qf = folds[qi.fold];
+        const int NT = qf.f.NT, A = qi.A, d = qi.d;
+        if (qi.kind == kQDiag) {
+            TileWork w{};
+            w.f = qf.f;
+            w.A = A;
+            diag_body<Q>(w, u.dg, tid, kTileThreads);
+            signal_add(qf.done + tile_index(NT, A, 0));
+        } else if (qi.kind == kQFinish) {
+            TileWork w{};
+            w.f = qf.f;
+            w.acc = qf.acc + (size_t)(2 * A + (d & 1)) * kTileCells;
+            w.A = A;
+            w.d = d;
+            w.nslot = qi.aux > 0 ? 1 : 0;
+            const int32_t* dn = qf.done;
+            auto pre = [&] { wait_ge(dn + tile_index(NT, A, 0), 1, dn + tile_index(NT, A + d, 0), 1, nullptr, 0, err); };
+            auto deps = [&] {
+                if (d >= 2)
+                    wait_ge(dn + tile_index(NT, A, d - 1), 1, dn + tile_index(NT, A + 1, d - 1), 1,
+                            qi.aux > 0 ? qf.bcnt + tile_index(NT, A, d) : nullptr, qi.aux, err);
+            };
+            tile_body<Q>(w, Rl, u.t, pre, deps);
+            signal_add(qf.done + tile_index(NT, A, d));
+        } else {
+            BetweenWork w{};
+            w.f = qf.f;
+            w.acc = qf.acc + (size_t)(2 * A + (d & 1)) * kTileCells;
+            w.A = A;
+            w.d = d;
+            w.c0 = qi.c0;
+            w.c1 = qi.c1;
+            w.atomic = qi.aux;
+            // tile (A, A+d-2) covers the row tiles (A, C <= A+d-2) and is the
+            // accumulator's previous reader; tile (c0, A+d) covers the column
+            // tiles (C >= c0, A+d)
+            wait_ge(qf.done + tile_index(NT, A, d - 2), 1, qf.done + tile_index(NT, qi.c0, A + d - qi.c0), 1,
+                    nullptr, 0, err);
+            // the strips were written during this launch: keep their loads
+            // (scalar loads among them) below the wait
+            uint64_t rs = (uint64_t)qf.f.RS, cs = (uint64_t)qf.f.CS;
+            asm volatile("" : "+s"(rs), "+s"(cs));
+            const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+            between_body<Q, kQueueRowsPerWave>(w, Rl, (const uint32_t*)rs, (const uint32_t*)cs, wave, tid & 63);
+            signal_add(qf.bcnt + tile_index(NT, A, d));
+        }
+    }
+}
+
+__global__ void k_scores(const FoldDesc* __restrict__ folds, int nfolds, int32_t* __restrict__ scores,
+                         const int32_t* __restrict__ err)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < nfolds) scores[e] = folds[e].F[folds[e].n];  // F(0, n) = D(1, n)
+    if (e < nfolds) scores[e] = (err && *err) ? -1 : folds[e].F[folds[e].n];  // F(0, n) = D(1, n)
+}
+
+__global__ void k_zero(int32_t* __restrict__ p, long long count)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = 0;
 }
 
 // S[i*n + j] = D(i+1, j+1) = F(i, j+1) for i <= j, 0 below the diagonal.
@@ -602,11 +802,97 @@ hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uin
     return dispatch(q, 2, items, nitems, R, s);
 }
 
-hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s)
+hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, const int32_t* err, hipStream_t s)
 {
     if (nfolds <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scores, dim3((nfolds + 255) / 256), dim3(256), 0, s, folds, nfolds, scores);
+    hipLaunchKernelGGL(k_scores, dim3((nfolds + 255) / 256), dim3(256), 0, s, folds, nfolds, scores, err);
     return hipGetLastError();
+}
+
+hipError_t launch_zero(int32_t* p, long long count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+namespace {
+template <int Q>
+hipError_t queue_q(const QItem* items, int nitems, const QFold* folds, const uint8_t* R, int* head, int* err,
+                   int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_queue<Q>, dim3(blocks), dim3(kTileThreads), 0, s, items, nitems, folds, R, head, err);
+    return hipGetLastError();
+}
+template <int Q>
+int occupancy_q()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_queue<Q>, kTileThreads, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+}  // namespace
+
+namespace {
+template <int Q>
+hipError_t stage_q(const TileWork* t, int nt, const BetweenWork* b, int nb, const uint8_t* R, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage<Q>, dim3(nt + nb), dim3(kTileThreads), 0, s, t, nt, b, R);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_stage(int q, const TileWork* titems, int ntile, const BetweenWork* bitems, int nbtw,
+                        const uint8_t* R, hipStream_t s)
+{
+    if (ntile + nbtw <= 0) return hipSuccess;
+    switch (q) {
+    case 1: return stage_q<1>(titems, ntile, bitems, nbtw, R, s);
+    case 2: return stage_q<2>(titems, ntile, bitems, nbtw, R, s);
+    case 3: return stage_q<3>(titems, ntile, bitems, nbtw, R, s);
+    case 4: return stage_q<4>(titems, ntile, bitems, nbtw, R, s);
+    case 5: return stage_q<5>(titems, ntile, bitems, nbtw, R, s);
+    case 6: return stage_q<6>(titems, ntile, bitems, nbtw, R, s);
+    case 7: return stage_q<7>(titems, ntile, bitems, nbtw, R, s);
+    case 8: return stage_q<8>(titems, ntile, bitems, nbtw, R, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_queue(int q, const QItem* items, int nitems, const QFold* folds, const uint8_t* R, int* head,
+                        int* err, int blocks, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (blocks <= 0) return hipErrorInvalidValue;
+    switch (q) {
+    case 1: return queue_q<1>(items, nitems, folds, R, head, err, blocks, s);
+    case 2: return queue_q<2>(items, nitems, folds, R, head, err, blocks, s);
+    case 3: return queue_q<3>(items, nitems, folds, R, head, err, blocks, s);
+    case 4: return queue_q<4>(items, nitems, folds, R, head, err, blocks, s);
+    case 5: return queue_q<5>(items, nitems, folds, R, head, err, blocks, s);
+    case 6: return queue_q<6>(items, nitems, folds, R, head, err, blocks, s);
+    case 7: return queue_q<7>(items, nitems, folds, R, head, err, blocks, s);
+    case 8: return queue_q<8>(items, nitems, folds, R, head, err, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int queue_blocks_per_cu(int q)
+{
+    switch (q) {
+    case 1: return occupancy_q<1>();
+    case 2: return occupancy_q<2>();
+    case 3: return occupancy_q<3>();
+    case 4: return occupancy_q<4>();
+    case 5: return occupancy_q<5>();
+    case 6: return occupancy_q<6>();
+    case 7: return occupancy_q<7>();
+    case 8: return occupancy_q<8>();
+    default: return 0;
+    }
 }
 
 hipError_t launch_expand(const int16_t* F, int ld, int n, int16_t* S, hipStream_t s)

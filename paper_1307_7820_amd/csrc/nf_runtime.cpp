@@ -159,14 +159,15 @@ Geom make_geom(int n, int q)
     return g;
 }
 
-static int between_target()
+// Between chunks per wavefront step (NF_BETWEEN_TARGET overrides).  Launches
+// per step want enough workgroups to fill the device; the persistent queue
+// pays a wait and a release per item, so it wants few, large chunks.
+int between_target(int mode)
 {
-    static int t = [] {
-        const char* e = getenv("NF_BETWEEN_TARGET");
-        int v = e ? atoi(e) : 0;
-        return v > 0 ? v : 1024;
-    }();
-    return t;
+    const char* e = getenv("NF_BETWEEN_TARGET");
+    const int env = e ? atoi(e) : 0;
+    if (env > 0) return env;
+    return mode == kModeQueue ? 128 : 1024;
 }
 
 // Append the between-group items of diagonal dd for the listed folds.  The
@@ -210,7 +211,7 @@ void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, in
     }
 }
 
-void build_schedule(const std::vector<int>& NTs, Schedule& sc)
+void build_schedule(const std::vector<int>& NTs, int target, Schedule& sc)
 {
     const int nf = (int)NTs.size();
     int stages = 0;
@@ -228,7 +229,6 @@ void build_schedule(const std::vector<int>& NTs, Schedule& sc)
     std::vector<std::pair<int, int>> folds_nt;
     folds_nt.reserve(nf);
     for (int f = 0; f < nf; ++f) folds_nt.push_back({f, NTs[f]});
-    const int target = between_target();
     int max_slots = 0;
     for (int sg = 0; sg < stages; ++sg) {
         if (sg == 0) {
@@ -264,6 +264,80 @@ void build_schedule(const std::vector<int>& NTs, Schedule& sc)
     for (size_t k = 0; k < sc.btw.size(); ++k) sc.btw[k].slot += (btw_stage[k] & 1) * max_slots;
     for (size_t k = 0; k < sc.tile.size(); ++k)
         if (sc.tile[k].nslot > 0) sc.tile[k].slot0 += ((tile_stage[k] - 1) & 1) * max_slots;
+}
+
+// The persistent fill's work queue: the schedule's own order (diagonal tiles,
+// then per step the finishes of diagonal s followed by the between chunks of
+// diagonal s+1).  Every wait of an item must be met by items placed before
+// it; that is checked here, so a plan whose queue could stall is refused.
+int build_queue(const Schedule& sc, const std::vector<int>& NTs, std::vector<QItem>& out)
+{
+    out.clear();
+    std::vector<std::vector<char>> done(NTs.size());
+    std::vector<std::vector<int>> chunks(NTs.size()), seen(NTs.size());
+    for (size_t f = 0; f < NTs.size(); ++f) {
+        const size_t tc = (size_t)tile_count(NTs[f]);
+        done[f].assign(tc, 0);
+        chunks[f].assign(tc, 0);
+        seen[f].assign(tc, 0);
+    }
+    for (const BetweenItem& b : sc.btw) chunks[b.fold][tile_index(NTs[b.fold], b.A, b.d)] += 1;
+    auto is_done = [&](int f, int A, int d) { return d >= 0 && A >= 0 && A + d < NTs[f] && done[f][tile_index(NTs[f], A, d)]; };
+    auto add_tile = [&](const TileItem& t, int kind) -> int {
+        const int f = t.fold, A = t.A, d = t.d, NT = NTs[f];
+        QItem q{kind, f, A, d, 0, 0, 0, 0};
+        if (kind == kQFinish) {
+            q.aux = chunks[f][tile_index(NT, A, d)];
+            bool ok = is_done(f, A, 0) && is_done(f, A + d, 0);
+            if (d >= 2) ok = ok && is_done(f, A, d - 1) && is_done(f, A + 1, d - 1) &&
+                             seen[f][tile_index(NT, A, d)] == q.aux;
+            if (!ok) return fail(NF_E_DEVICE, "work queue order broken at finish (%d, %d) of fold %d", A, A + d, f);
+        }
+        out.push_back(q);
+        done[f][tile_index(NT, A, d)] = 1;
+        return NF_OK;
+    };
+    for (int sg = 0; sg < sc.stages; ++sg) {
+        int rc;
+        if (sg == 0) {
+            for (const TileItem& t : sc.diag)
+                if ((rc = add_tile(t, kQDiag))) return rc;
+        } else {
+            for (int k = 0; k < sc.tile_cnt[sg]; ++k)
+                if ((rc = add_tile(sc.tile[sc.tile_off[sg] + k], kQFinish))) return rc;
+        }
+        for (int k = 0; k < sc.btw_cnt[sg]; ++k) {
+            const BetweenItem& b = sc.btw[sc.btw_off[sg] + k];
+            const int f = b.fold, NT = NTs[f];
+            if (!(b.d >= 4 && b.c0 >= b.A + 2 && b.c1 <= b.A + b.d - 1 && b.c0 < b.c1 && is_done(f, b.A, b.d - 2) &&
+                  is_done(f, b.c0, b.A + b.d - b.c0)))
+                return fail(NF_E_DEVICE, "work queue order broken at between (%d, %d) of fold %d", b.A, b.A + b.d, f);
+            out.push_back(QItem{kQBetween, f, b.A, b.d, b.c0, b.c1, b.pad0, 0});
+            seen[f][tile_index(NT, b.A, b.d)] += 1;
+        }
+    }
+    return NF_OK;
+}
+
+// Execution of a new plan.  NF_MODE = "staged", "fused" or "queue" forces
+// one (see PlanMode); otherwise fused steps when the tiles of one step are
+// few (the step is latency-bound: one launch and no cross-stream wait per
+// step is cheapest), staged steps when the between chunks of a step fill the
+// device (the two-stream form runs them at full occupancy).  Measured on
+// MI355X: fused is faster for one fold up to n = 12000, staged at n = 16000
+// and for a batch of 4096 folds.
+constexpr long long kFusedMaxTilesPerSide = 208;
+
+int plan_mode_for(const std::vector<int>& NTs)
+{
+    if (const char* e = getenv("NF_MODE")) {  // read per plan: cached plans keep their mode
+        if (strcmp(e, "queue") == 0) return kModeQueue;
+        if (strcmp(e, "fused") == 0) return kModeFused;
+        if (strcmp(e, "staged") == 0) return kModeStaged;
+    }
+    long long sum = 0;
+    for (int nt : NTs) sum += nt;
+    return sum <= kFusedMaxTilesPerSide ? (int)kModeFused : (int)kModeStaged;
 }
 
 // ------------------------------------------------------------------ plans
@@ -359,9 +433,67 @@ int plan_allocate(Plan& p)
         HIPCHK(hipMemcpyAsync(p.d_tile.p, wt.data(), wt.size() * sizeof(TileWork), hipMemcpyHostToDevice, s));
     if (!wb.empty())
         HIPCHK(hipMemcpyAsync(p.d_btw.p, wb.data(), wb.size() * sizeof(BetweenWork), hipMemcpyHostToDevice, s));
+    if (p.mode == kModeQueue) {
+        std::vector<int> NTs;
+        for (auto& g : p.geom) NTs.push_back(g.NT);
+        std::vector<QItem> qi;
+        if ((rc = build_queue(sc, NTs, qi))) return rc;
+        p.nqitems = (int)qi.size();
+        // counters: [head, err, 14 pad] then per fold done[tiles], bcnt[tiles]
+        size_t acc_cells = 0;
+        long long ints = 16;
+        for (int nt : NTs) {
+            acc_cells += (size_t)2 * nt * kTileCells;
+            ints += 2 * tile_count(nt);
+        }
+        p.qstate_ints = ints;
+        if ((rc = p.d_qitems.alloc(std::max<size_t>(1, qi.size()) * sizeof(QItem)))) return rc;
+        if ((rc = p.d_qfolds.alloc(std::max<size_t>(1, fd.size()) * sizeof(QFold)))) return rc;
+        if ((rc = p.d_qacc.alloc(std::max<size_t>(1, acc_cells) * sizeof(int32_t)))) return rc;
+        if ((rc = p.d_qstate.alloc((size_t)ints * sizeof(int32_t)))) return rc;
+        std::vector<QFold> qf(fd.size());
+        int32_t* acc = (int32_t*)p.d_qacc.p;
+        int32_t* st = (int32_t*)p.d_qstate.p + 16;
+        for (size_t f = 0; f < fd.size(); ++f) {
+            const long long tc = tile_count(NTs[f]);
+            qf[f].f = fd[f];
+            qf[f].acc = acc;
+            qf[f].done = st;
+            qf[f].bcnt = st + tc;
+            qf[f].pad = nullptr;
+            acc += (size_t)2 * NTs[f] * kTileCells;
+            st += 2 * tc;
+        }
+        // accumulators start at zero; every run leaves them zero again
+        HIPCHK(hipMemsetAsync(p.d_qacc.p, 0, p.d_qacc.bytes, s));
+        if (!qi.empty())
+            HIPCHK(hipMemcpyAsync(p.d_qitems.p, qi.data(), qi.size() * sizeof(QItem), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(p.d_qfolds.p, qf.data(), qf.size() * sizeof(QFold), hipMemcpyHostToDevice, s));
+        Context& c = ctx();
+        if (!c.queue_blocks[p.q]) c.queue_blocks[p.q] = queue_blocks_per_cu(p.q);
+        if (c.queue_blocks[p.q] <= 0) return fail(NF_E_DEVICE, "persistent fill kernel cannot be resident (q = %d)", p.q);
+    }
     HIPCHK(hipStreamSynchronize(s));
     p.device_bytes = p.arena.bytes + p.d_folds.bytes + p.d_diag.bytes + p.d_tile.bytes + p.d_btw.bytes +
-                     p.d_part.bytes + p.d_scores.bytes;
+                     p.d_part.bytes + p.d_scores.bytes + p.d_qitems.bytes + p.d_qfolds.bytes + p.d_qacc.bytes +
+                     p.d_qstate.bytes;
+    return NF_OK;
+}
+
+// The persistent fill: zero the counters (a kernel, so the run can be
+// captured), drain the queue with every resident workgroup, read the scores.
+static int plan_enqueue_queue(Plan& p, hipStream_t s)
+{
+    const uint8_t* R = nullptr;
+    int rc = get_R(p.q, &R);
+    if (rc) return rc;
+    Context& c = ctx();
+    int32_t* st = (int32_t*)p.d_qstate.p;
+    const int blocks = std::max(1, std::min(p.nqitems, c.queue_blocks[p.q] * c.num_cu));
+    HIPCHK(launch_zero(st, p.qstate_ints, s));
+    HIPCHK(launch_queue(p.q, (const QItem*)p.d_qitems.p, p.nqitems, (const QFold*)p.d_qfolds.p, R, st, st + 1, blocks,
+                        s));
+    HIPCHK(launch_scores((const FoldDesc*)p.d_folds.p, (int)p.geom.size(), (int32_t*)p.d_scores.p, st + 1, s));
     return NF_OK;
 }
 
@@ -372,8 +504,33 @@ int plan_allocate(Plan& p)
 //     finish(s)    after between(s-1)  (its between maxima)
 //     between(s)   after finish(s-1)   (its inputs; also frees its accumulators)
 // Under graph capture the events become graph edges.
+// Fused steps: one launch per step on one stream.  Kernel order alone gives
+//     finish(s)  after between(s)  (in launch s-1)
+//     between(s+1) after finish(s-1) (launch s-1)
+static int plan_enqueue_fused(Plan& p, hipStream_t s)
+{
+    const uint8_t* R = nullptr;
+    int rc = get_R(p.q, &R);
+    if (rc) return rc;
+    const Schedule& sc = p.sc;
+    for (int sg = 0; sg < sc.stages; ++sg) {
+        if (sg == 0) {
+            HIPCHK(launch_diag(p.q, (const TileWork*)p.d_diag.p, (int)sc.diag.size(), s));
+            if (sc.btw_cnt[0] > 0)
+                HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[0], sc.btw_cnt[0], R, s));
+        } else {
+            HIPCHK(launch_stage(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg],
+                                (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R, s));
+        }
+    }
+    HIPCHK(launch_scores((const FoldDesc*)p.d_folds.p, (int)p.geom.size(), (int32_t*)p.d_scores.p, nullptr, s));
+    return NF_OK;
+}
+
 int plan_enqueue_direct(Plan& p, hipStream_t s)
 {
+    if (p.mode == kModeQueue) return plan_enqueue_queue(p, s);
+    if (p.mode == kModeFused) return plan_enqueue_fused(p, s);
     const uint8_t* R = nullptr;
     int rc = get_R(p.q, &R);
     if (rc) return rc;
@@ -400,12 +557,28 @@ int plan_enqueue_direct(Plan& p, hipStream_t s)
     // join the side stream back into s
     HIPCHK(hipEventRecord(ev_btw, s2));
     HIPCHK(hipStreamWaitEvent(s, ev_btw, 0));
-    HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, s));
+    HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, nullptr, s));
     return NF_OK;
 }
 
 // Valid (non-padding) columns of tile column B of a fold.
 static int valid_cols(const Geom& g, int T, int B) { return std::max(0, std::min(T, g.n + 1 - B * T)); }
+
+// Terms of Eq. 1 evaluated one by one inside an off-diagonal tile with vb
+// valid columns: for cell (i, j) the split points in the tile's own rows
+// (T-1-i of them) and columns (j), plus the pairing term.
+static double tile_terms(int T, int vb)
+{
+    return (double)vb * T * (T - 1) / 2 + (double)T * vb * (vb - 1) / 2 + (double)T * vb;
+}
+// The same for a main-diagonal tile of v valid posts: cell (i, i+t) has t-1
+// split points and one pairing term (t >= 1).
+static double diag_terms(int v)
+{
+    double s = 0;
+    for (int t = 1; t < v; ++t) s += (double)(v - t) * t;
+    return s;
+}
 
 int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
 {
@@ -416,12 +589,14 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
     const FoldDesc* folds = (const FoldDesc*)p.d_folds.p;
     const Schedule& sc = p.sc;
     // algorithmic work per launch, from the work lists
-    std::vector<double> tile_lk(sc.stages, 0), tile_cells(sc.stages, 0), btw_lk(sc.stages, 0);
+    std::vector<double> tile_lk(sc.stages, 0), tile_sp(sc.stages, 0), tile_cells(sc.stages, 0),
+        btw_lk(sc.stages, 0);
     for (int sg = 0; sg < sc.stages; ++sg) {
         for (int k = 0; k < sc.tile_cnt[sg]; ++k) {
             const TileItem& it = sc.tile[sc.tile_off[sg] + k];
             const int vb = valid_cols(p.geom[it.fold], T, it.A + it.d);
             tile_lk[sg] += (double)std::min(std::max(it.d - 1, 0), 2) * G * T * vb;
+            tile_sp[sg] += tile_terms(T, vb);
             tile_cells[sg] += (double)T * vb;
         }
         for (int k = 0; k < sc.btw_cnt[sg]; ++k) {
@@ -430,10 +605,11 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
             btw_lk[sg] += (double)(it.c1 - it.c0) * G * T * vb;
         }
     }
-    double diag_cells = 0;
+    double diag_cells = 0, diag_sp = 0;
     for (auto& it : sc.diag) {
         const int v = valid_cols(p.geom[it.fold], T, it.A);
         diag_cells += (double)v * (v + 1) / 2;
+        diag_sp += diag_terms(v);
     }
     std::vector<hipEvent_t> ev;
     auto fresh = [&]() {
@@ -442,32 +618,56 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
         ev.push_back(e);
         return e;
     };
-    struct Rec { int kind; hipEvent_t a, b; double lk, cells; };
+    struct Rec { int kind; hipEvent_t a, b; double lk, sp, cells; };
     std::vector<Rec> recs;
-    for (int r = 0; r < reps; ++r) {
-        hipEvent_t a = fresh(), b = fresh();
-        HIPCHK(hipEventRecord(a, s));
-        HIPCHK(launch_diag(p.q, (const TileWork*)p.d_diag.p, (int)sc.diag.size(), s));
-        HIPCHK(hipEventRecord(b, s));
-        recs.push_back({0, a, b, 0.0, diag_cells});
+    if (p.mode == kModeQueue) {
+        double lk = 0, sp = diag_sp, cells = diag_cells;
         for (int sg = 0; sg < sc.stages; ++sg) {
-            if (sg >= 1 && sc.tile_cnt[sg] > 0) {
-                a = fresh(); b = fresh();
-                HIPCHK(hipEventRecord(a, s));
-                HIPCHK(launch_tile(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R, s));
-                HIPCHK(hipEventRecord(b, s));
-                recs.push_back({1, a, b, tile_lk[sg], tile_cells[sg]});
-            }
-            if (sc.btw_cnt[sg] > 0) {
-                a = fresh(); b = fresh();
-                HIPCHK(hipEventRecord(a, s));
-                HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg],
-                                      R, s));
-                HIPCHK(hipEventRecord(b, s));
-                recs.push_back({2, a, b, btw_lk[sg], 0.0});
-            }
+            lk += tile_lk[sg] + btw_lk[sg];
+            sp += tile_sp[sg];
+            cells += tile_cells[sg];
         }
-        HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, s));
+        Context& c = ctx();
+        int32_t* st = (int32_t*)p.d_qstate.p;
+        const int blocks = std::max(1, std::min(p.nqitems, c.queue_blocks[p.q] * c.num_cu));
+        for (int r = 0; r < reps; ++r) {
+            HIPCHK(launch_zero(st, p.qstate_ints, s));
+            hipEvent_t a = fresh(), b = fresh();
+            HIPCHK(hipEventRecord(a, s));
+            HIPCHK(launch_queue(p.q, (const QItem*)p.d_qitems.p, p.nqitems, (const QFold*)p.d_qfolds.p, R, st, st + 1,
+                                blocks, s));
+            HIPCHK(hipEventRecord(b, s));
+            recs.push_back({3, a, b, lk, sp, cells});
+            HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, st + 1, s));
+        }
+    } else {
+        for (int r = 0; r < reps; ++r) {
+            hipEvent_t a = fresh(), b = fresh();
+            HIPCHK(hipEventRecord(a, s));
+            HIPCHK(launch_diag(p.q, (const TileWork*)p.d_diag.p, (int)sc.diag.size(), s));
+            HIPCHK(hipEventRecord(b, s));
+            recs.push_back({0, a, b, 0.0, diag_sp, diag_cells});
+            for (int sg = 0; sg < sc.stages; ++sg) {
+                if (sg >= 1 && sc.tile_cnt[sg] > 0) {
+                    a = fresh();
+                    b = fresh();
+                    HIPCHK(hipEventRecord(a, s));
+                    HIPCHK(launch_tile(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R, s));
+                    HIPCHK(hipEventRecord(b, s));
+                    recs.push_back({1, a, b, tile_lk[sg], tile_sp[sg], tile_cells[sg]});
+                }
+                if (sc.btw_cnt[sg] > 0) {
+                    a = fresh();
+                    b = fresh();
+                    HIPCHK(hipEventRecord(a, s));
+                    HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R,
+                                          s));
+                    HIPCHK(hipEventRecord(b, s));
+                    recs.push_back({2, a, b, btw_lk[sg], 0.0, 0.0});
+                }
+            }
+            HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, nullptr, s));
+        }
     }
     HIPCHK(hipStreamSynchronize(s));
     for (auto& rc2 : recs) {
@@ -477,6 +677,7 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
         out->launches[rc2.kind] += 1;
         out->ms[rc2.kind] += ms;
         out->lookups[rc2.kind] += rc2.lk;
+        out->splits[rc2.kind] += rc2.sp;
         out->cells[rc2.kind] += rc2.cells;
     }
     for (auto e : ev) (void)hipEventDestroy(e);
@@ -520,7 +721,8 @@ int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out)
         p->geom.push_back(make_geom(n, q));
         NTs.push_back(p->geom.back().NT);
     }
-    build_schedule(NTs, p->sc);
+    p->mode = plan_mode_for(NTs);
+    build_schedule(NTs, between_target(p->mode), p->sc);
     int rc = plan_allocate(*p);
     if (rc) return rc;
     out = std::move(p);

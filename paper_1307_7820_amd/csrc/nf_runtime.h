@@ -57,13 +57,27 @@ struct Schedule {
     std::vector<int> tile_off, tile_cnt, btw_off, btw_cnt;
 };
 
+// How a plan's fill runs:
+//   staged: per wavefront step, the tile finishes of diagonal s on one stream
+//           and the between chunks of diagonal s+1 on a second one;
+//   fused:  per step one launch holding both (one stream, no cross-stream
+//           waits);
+//   queue:  one persistent launch draining a dependency-ordered work queue.
+enum PlanMode { kModeStaged = 0, kModeQueue = 1, kModeFused = 2 };
+
 struct Plan {
     int q = 8;
+    int mode = kModeStaged;
     std::vector<Geom> geom;
     std::vector<FoldDesc> h_folds;
     Schedule sc;
     DevBuf arena, d_folds, d_diag, d_tile, d_btw, d_part, d_scores;
     DevBuf d_S;  // expand target for host copies of tables
+    // persistent-queue mode: items, per-fold descriptors, accumulators and
+    // the counters zeroed before every run ([head, err, pad..., done/bcnt])
+    DevBuf d_qitems, d_qfolds, d_qacc, d_qstate;
+    int nqitems = 0;
+    long long qstate_ints = 0;
     size_t device_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -86,6 +100,7 @@ struct Context {
     DevBuf R[NF_Q_MAX + 1];
     std::vector<std::pair<long long, std::unique_ptr<Plan>>> plans;  // LRU, most recent last
     int tuned_q[kTuneBuckets] = {0};
+    int queue_blocks[NF_Q_MAX + 1] = {0};  // resident persistent workgroups per CU, by q
     bool tune_loaded = false;
 };
 
@@ -100,12 +115,15 @@ Geom make_geom(int n, int q);
 void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, int target,
                     std::vector<BetweenItem>& out, int* next_slot,
                     std::vector<std::vector<std::pair<int, int>>>& pending);
-void build_schedule(const std::vector<int>& NTs, Schedule& sc);
+void build_schedule(const std::vector<int>& NTs, int target, Schedule& sc);
+int between_target(int mode);
 int plan_allocate(Plan& p);
 TileWork to_work(const TileItem& it, const std::vector<FoldDesc>& fd, int32_t* acc_base);
 BetweenWork to_work(const BetweenItem& it, const std::vector<FoldDesc>& fd, int32_t* acc_base);
 int plan_enqueue(Plan& p, hipStream_t s);
 int plan_enqueue_direct(Plan& p, hipStream_t s);
+int build_queue(const Schedule& sc, const std::vector<int>& NTs, std::vector<QItem>& out);
+int plan_mode_for(const std::vector<int>& NTs);
 int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out);
 int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out);
 int single_plan(int n, int q, Plan** out);

@@ -165,3 +165,20 @@ def test_autotune_picks_and_caches(nf):
     s = gen.iid_sequence(1500, [111, 0])
     score, T = nf.nf_fold(s, q=0, table=True)
     assert np.array_equal(T, oracle.fold_table(s))
+
+
+def test_results_independent_of_stale_device_memory(nf):
+    # For q = 3, 5, 6, 7 a tile holds T < 64 posts and its packed-word lines
+    # have padding rows and columns; they must never carry over whatever the
+    # device memory held before.  Fill freed memory with junk, then refold.
+    import torch
+    x = torch.full((1 << 28,), 0x7F7F7F7F, dtype=torch.int32, device="cuda")
+    del x
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    nf.nf_shutdown()
+    for q in (3, 5, 6, 7):
+        for k, n in enumerate((129, 250, 700)):
+            s = gen.iid_sequence(n, [112, q, k])
+            score, T = nf.nf_fold(s, q=q, table=True)
+            assert np.array_equal(T, oracle.fold_table(s)), (q, n)
