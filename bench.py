@@ -112,7 +112,7 @@ def roofline(nf, codes, n, q, reps=3):
     from the work lists; duration = HIP events around each launch on the
     launching stream."""
     prof = nf.nf_profile_fold(codes, n, q, reps)
-    ks = [i for i in range(4) if prof.launches[i] > 0]
+    ks = [i for i in range(len(nf.KERNEL_NAMES)) if prof.launches[i] > 0]
     k = max(ks, key=lambda i: prof.ms[i])
     name = nf.KERNEL_NAMES[k]
     per_launch_s = prof.ms[k] / 1e3 / prof.launches[k]

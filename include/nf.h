@@ -194,18 +194,20 @@ int nf_autotune(int n, int qmin, int qmax, int reps);
  * nf_fold_dev).  Runs the fill reps times without a graph, each launch
  * bracketed by HIP events recorded on stream, and sums per kernel class k:
  * 0 = main-diagonal tiles, 1 = tile finish, 2 = between-group lookups (the
- * per-diagonal launches), 3 = the persistent fill (the whole table in one
- * launch; the default execution, see nf_fold).  For the class the run uses:
+ * launches of the staged execution), 3 = the persistent fill (the whole table
+ * in one launch), 4 = one fused step (finishes of a diagonal and the
+ * between-group chunks of the next); the fill runs in the execution its
+ * workspace uses (see nf_fold).  For every class:
  * lookups[k] counts the Four-Russians steps of Eq. 3 on table cells (padding
  * excluded), splits[k] the terms of Eq. 1 evaluated one by one inside tiles
  * (split points within a tile's own rows or columns, plus the pairing term),
  * cells[k] the table cells finished.  Synchronous. */
 typedef struct {
-    int64_t launches[4];
-    double ms[4];
-    double lookups[4];
-    double splits[4];
-    double cells[4];
+    int64_t launches[5];
+    double ms[5];
+    double lookups[5];
+    double splits[5];
+    double cells[5];
     int q, tile, tiles_per_side, stages;
 } nf_kernel_profile_t;
 int nf_profile_fold(const uint8_t* d_codes, int n, int q, int reps, void* stream, nf_kernel_profile_t* out);

@@ -640,6 +640,27 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
             recs.push_back({3, a, b, lk, sp, cells});
             HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, st + 1, s));
         }
+    } else if (p.mode == kModeFused) {
+        for (int r = 0; r < reps; ++r) {
+            hipEvent_t a = fresh(), b = fresh();
+            HIPCHK(hipEventRecord(a, s));
+            HIPCHK(launch_diag(p.q, (const TileWork*)p.d_diag.p, (int)sc.diag.size(), s));
+            if (sc.btw_cnt[0] > 0)
+                HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[0], sc.btw_cnt[0], R, s));
+            HIPCHK(hipEventRecord(b, s));
+            recs.push_back({0, a, b, btw_lk[0], diag_sp, diag_cells});
+            for (int sg = 1; sg < sc.stages; ++sg) {
+                if (sc.tile_cnt[sg] + sc.btw_cnt[sg] == 0) continue;
+                a = fresh();
+                b = fresh();
+                HIPCHK(hipEventRecord(a, s));
+                HIPCHK(launch_stage(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg],
+                                    (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R, s));
+                HIPCHK(hipEventRecord(b, s));
+                recs.push_back({4, a, b, tile_lk[sg] + btw_lk[sg], tile_sp[sg], tile_cells[sg]});
+            }
+            HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, nullptr, s));
+        }
     } else {
         for (int r = 0; r < reps; ++r) {
             hipEvent_t a = fresh(), b = fresh();
