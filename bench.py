@@ -109,8 +109,8 @@ def roofline(nf, codes, n, q, reps=3):
 
     Algorithmic work per launch = 2.5 VALU lane-ops per Eq. 3 lookup + 2 per
     Eq. 1 term evaluated one by one inside a tile (add, max), both counted
-    from the work lists; duration = HIP events around each launch on the
-    launching stream."""
+    from the work lists; duration = the kernel's own start and end, recorded
+    into HIP events by its dispatch on the launching stream."""
     prof = nf.nf_profile_fold(codes, n, q, reps)
     ks = [i for i in range(len(nf.KERNEL_NAMES)) if prof.launches[i] > 0]
     k = max(ks, key=lambda i: prof.ms[i])

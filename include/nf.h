@@ -191,8 +191,10 @@ int nf_autotune(int n, int qmin, int qmax, int reps);
 
 /* ---- Diagnostics ----
  * Per-kernel timing of the fill of one sequence given as device codes (as in
- * nf_fold_dev).  Runs the fill reps times without a graph, each launch
- * bracketed by HIP events recorded on stream, and sums per kernel class k:
+ * nf_fold_dev).  Runs the fill reps times on stream without a graph; each
+ * launch is timed by a pair of HIP events that its own dispatch records when
+ * the kernel starts and ends (hipExtLaunchKernelGGL), and the durations are
+ * summed per kernel class k:
  * 0 = main-diagonal tiles, 1 = tile finish, 2 = between-group lookups (the
  * launches of the staged execution), 3 = the persistent fill (the whole table
  * in one launch), 4 = one fused step (finishes of a diagonal and the

@@ -94,7 +94,7 @@ static_assert(sizeof(BetweenWork) == 80, "BetweenWork layout");
 // One fused wavefront step: ntile tile finishes and nbtw between chunks of
 // the next diagonal in one launch of kTileThreads-thread workgroups.
 hipError_t launch_stage(int q, const TileWork* titems, int ntile, const BetweenWork* bitems, int nbtw,
-                        const uint8_t* R, hipStream_t s);
+                        const uint8_t* R, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Work queue of the persistent fill (one launch per plan run).  Items are
 // claimed in array order through an atomic head counter and each item only
@@ -124,7 +124,7 @@ static_assert(sizeof(QFold) == 80, "QFold layout");
 // (device ints) and every done/bcnt counter must be zero at launch.  err is
 // set when a dependency wait exceeds its time limit (the run is then invalid).
 hipError_t launch_queue(int q, const QItem* items, int nitems, const QFold* folds, const uint8_t* R, int* head,
-                        int* err, int blocks, hipStream_t s);
+                        int* err, int blocks, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Resident workgroups per CU of the persistent fill for q (0 on error).
 int queue_blocks_per_cu(int q);
 // Zero `count` ints at p (a fill kernel: safe inside captured graphs).
@@ -132,9 +132,13 @@ hipError_t launch_zero(int32_t* p, long long count, hipStream_t s);
 
 hipError_t launch_precompute_R(int q, uint8_t* R, hipStream_t s);
 hipError_t launch_copy_codes(const uint8_t* src, int n, uint8_t* dst, int padded, hipStream_t s);
-hipError_t launch_diag(int q, const TileWork* items, int nitems, hipStream_t s);
-hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, hipStream_t s);
-hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, hipStream_t s);
+// With events e0/e1 the dispatch records the kernel's own start and end.
+hipError_t launch_diag(int q, const TileWork* items, int nitems, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
+hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, hipStream_t s,
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, hipStream_t s,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // scores[f] = F(0, n_f); -1 for every fold when err is non-null and set.
 hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, const int32_t* err, hipStream_t s);
 hipError_t launch_expand(const int16_t* F, int ld, int n, int16_t* S, hipStream_t s);

@@ -17,6 +17,8 @@
 // between-group work is split into partial slots.
 #include "nf_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace nf {
 
 namespace {
@@ -202,20 +204,24 @@ __global__ __launch_bounds__(kThreads) void k_between(const BetweenWork* __restr
 // Rows are finished bottom-up, one max-plus vector-matrix product per row.
 //
 // Work split: wave w owns the 8 columns J_w = [8w, 8w+8) of every row.  Lane
-// l = 8g + c holds column j = 8w + c and the accumulators of rows
-// 8g..8g+7, and for the closure it reduces the split points j' in
-// [8g, 8g+8) (its 8 entries of U sit in registers); the 8 lanes of a column
-// then combine their partial maxima with a butterfly inside the wavefront
-// (DPP row rotation and the gfx950 16/32-lane swaps).  Each row costs one
-// workgroup barrier: the row's Q is published in LDS before it, the row's
-// cells and the next row's Q after it.  The pairing partner of the first
-// column of a slice lives in the wavefront to the left, so that one term is
-// added by the readers of Q instead.  A finished row is pushed (its L terms)
-// into the rows above it in its 8-row block one split at a time; when a
-// whole block is finished and q divides 8 its q-groups reach every row above
-// the block through one R lookup per group (Eq. 3: row words of tile (A, A),
-// column words of this tile).  For other q every row is pushed one split at
-// a time.
+// l = 8g + c holds column j = 8w + c and the accumulators of the rows
+// i = 8b + g (b = 0..7: one row in each 8-row block), and for the closure it
+// reduces the split points j' in [8g, 8g+8) (its 8 entries of U sit in
+// registers); the 8 lanes of a column then combine their partial maxima with
+// a butterfly inside the wavefront (DPP row rotation and the gfx950 16/32-lane
+// swaps).  Each row costs one workgroup barrier: the row's Q is published in
+// LDS before it, the row's cells and the next row's Q after it.  The pairing
+// partner of the first column of a slice lives in the wavefront to the left,
+// so that one term is added by the readers of Q instead.
+//
+// A finished row is pushed (its L terms) into the rows above it in its 8-row
+// block, one split each, by the lanes that hold those rows; when a whole
+// block is finished and q divides 8 its q-groups reach every row above the
+// block through one R lookup per group (Eq. 3: row words of tile (A, A),
+// column words of this tile).  For other q every row is pushed into every row
+// above it one split at a time.  The groups of the two end tiles (C = A+1,
+// C = B-1) for the rows of block b-1 are looked up while block b is closed,
+// a few per row, in the slack of the row steps.
 constexpr int kTileThreads = 512;
 constexpr int kNeg = -(1 << 20);  // stands for minus infinity; sums stay far from overflow
 
@@ -242,9 +248,14 @@ struct TileLds {
     static constexpr bool kBlockFR = (8 % Q) == 0;  // q-groups tile the 8-row blocks
     static constexpr bool kStageEdges = G <= 16;    // end-tile words fit in LDS
     int32_t Xs[64 * 64];  // finished cells, row-major
-    int32_t Lt[64 * 64];  // Lt[i*64 + i''] = L(i'', i) for i'' < i < T, else -inf
-    uint32_t LW[kBlockFR ? G * 64 : 4];        // row words of tile (A, A), [k][row]
-    uint32_t EW[kStageEdges ? 6 * G * 64 : 4];  // [edge][base|bits|col][k][64]
+    // Lp[i*kLS + 8g + b] = L(8b+g, i) for 8b+g < i < T, else -inf; the row
+    // stride kLS = 68 keeps 16-byte rows and spreads the transposed writes
+    // over the banks
+    static constexpr int kLS = 68;
+    int32_t Lp[64 * kLS];
+    uint32_t LW[kBlockFR ? G * 64 : 4];  // LW[k*64 + 8g + b]: row word of row 8b+g, group k, tile (A, A)
+    uint2 EB[kStageEdges ? 2 * G * 64 : 1];      // EB[(e*G + k)*64 + row] = {base, bits}, end tile e
+    uint32_t EC[kStageEdges ? 2 * G * 64 : 1];  // EC[(e*G + k)*64 + col] = column word, end tile e
     int32_t Qs[2][64];    // Q of the row being closed (double-buffered)
     int32_t hrow[64], hcol[64];
     uint8_t ca[64], cb[64];
@@ -265,12 +276,15 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
     constexpr int SW = state_words(Q);
     constexpr int RW = row_words(Q);
     constexpr bool kBlockFR = TileLds<Q>::kBlockFR;
-    constexpr int GPB = kBlockFR ? 8 / Q : 1;   // groups per block
+    constexpr int GPB = kBlockFR ? 8 / Q : 1;  // groups per block
     constexpr bool kStageEdges = TileLds<Q>::kStageEdges;
+    constexpr int NE = kStageEdges ? 2 * G : 1;  // end-tile lookups per row (both edges)
+    constexpr int LS = TileLds<Q>::kLS;
     int32_t* Xs = s.Xs;
-    int32_t* Lt = s.Lt;
+    int32_t* Lp = s.Lp;
     uint32_t* LW = s.LW;
-    uint32_t* EW = s.EW;
+    uint2* EB = s.EB;
+    uint32_t* EC = s.EC;
     int32_t (*Qs)[64] = s.Qs;
     int32_t* hrow = s.hrow;
     int32_t* hcol = s.hcol;
@@ -284,11 +298,13 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int g = lane >> 3, c = lane & 7;
-    const int j = wave * 8 + c;  // this lane's column
-    const int r0 = g * 8;        // first of this lane's 8 rows
+    const int j = wave * 8 + c;  // this lane's column; its rows are 8b + g
     const long long ld = f.ld;
     const int aT = A * T, bT = B * T;
-    const int16_t* F = f.F;
+    const NF_GLOBAL int16_t* F = (const NF_GLOBAL int16_t*)f.F;  // global loads: see the output pointers
+    const NF_GLOBAL uint8_t* codes = (const NF_GLOBAL uint8_t*)f.codes;
+    const NF_GLOBAL uint32_t* RSr = (const NF_GLOBAL uint32_t*)f.RS;
+    const NF_GLOBAL uint32_t* CSr = (const NF_GLOBAL uint32_t*)f.CS;
     const int nedge = d >= 3 ? 2 : (d == 2 ? 1 : 0);
 
     // ---- prologue, part 1: L, U and the codes
@@ -303,34 +319,55 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
     int ureg[8];  // U(8g + t, j); -inf where the split point is not left of column j
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        const int jp = r0 + t;
+        const int jp = 8 * g + t;
         ureg[t] = (jp <= j && j < T) ? (int)F[(bT + jp) * ld + bT + j] : kNeg;
     }
     if (tid < 64) {
-        ca[tid] = f.codes[aT + tid];      // S_{a+1}, a = AT + i
-        cb[tid] = f.codes[bT + tid - 1];  // S_b,     b = BT + j  (BT >= 1)
+        ca[tid] = codes[aT + tid];      // S_{a+1}, a = AT + i
+        cb[tid] = codes[bT + tid - 1];  // S_b,     b = BT + j  (BT >= 1)
     }
 
     // ---- prologue, part 2: the between maxima, the end tiles and the halo
     wait_main();
-    int acc[8];
-    int32_t* accp = it.acc + r0 * 64 + j;
+    int acc[8];  // acc[b]: row 8b + g, column j
+    NF_GLOBAL int32_t* accp = (NF_GLOBAL int32_t*)(it.acc + g * 64 + j);
     if (it.nslot > 0) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) acc[r] = accp[r * 64];
+        for (int b = 0; b < 8; ++b) acc[b] = accp[b * 512];
     } else {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) acc[r] = 0;
+        for (int b = 0; b < 8; ++b) acc[b] = 0;
     }
     if constexpr (kStageEdges) {
-        // edge e: C = A+1 (e = 0) and C = B-1 (e = 1); row block of (A, C)
-        // (bases, bits) then column block of (C, B)
-        for (int x = tid; x < nedge * 3 * G * 16; x += kTileThreads) {
-            const int e = x / (3 * G * 16), o = x % (3 * G * 16);
+        // edge e: C = A+1 (e = 0) and C = B-1 (e = 1); {base, bits} per row
+        // of tile (A, C), column words of tile (C, B).  An end tile that does
+        // not exist (e >= nedge) gets zero words: its lookups then give 0,
+        // which no accumulator is below, so every lookup can run unguarded.
+        // (The loads stay inside the fold's tile arrays either way.)
+        constexpr int kIter = (2 * G * 64 + kTileThreads - 1) / kTileThreads;
+        uint32_t rb[kIter], rh[kIter], cw[kIter];
+#pragma unroll
+        for (int u = 0; u < kIter; ++u) {
+            const int x = tid + u * kTileThreads;
+            const int eg = x >> 6, r = x & 63;
+            const int e = eg / G, k = eg - e * G;
             const int C = e == 0 ? A + 1 : B - 1;
-            const uint32_t* src = o < 2 * G * 16 ? f.RS + tile_index(f.NT, A, C - A) * RW + o * 4
-                                                 : f.CS + tile_index(f.NT, C, B - C) * SW + (o - 2 * G * 16) * 4;
-            *reinterpret_cast<uint4*>(&EW[e * 3 * G * 64 + o * 4]) = *reinterpret_cast<const uint4*>(src);
+            rb[u] = rh[u] = cw[u] = 0;
+            if (x < 2 * G * 64) {
+                const NF_GLOBAL uint32_t* rs = RSr + tile_index(f.NT, A, C - A) * RW + k * 64 + r;
+                rb[u] = rs[0];
+                rh[u] = rs[G * 64];
+                cw[u] = CSr[tile_index(f.NT, C, B - C) * SW + k * 64 + r];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kIter; ++u) {
+            const int x = tid + u * kTileThreads;
+            if (x < 2 * G * 64) {
+                const bool live = (x >> 6) < nedge * G;
+                EB[x] = live ? make_uint2(rb[u], rh[u]) : make_uint2(0u, 0u);
+                EC[x] = live ? cw[u] : 0u;
+            }
         }
     }
     if (tid < T) {
@@ -339,70 +376,65 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
         const int hc_r = aT + 1 + tid, hc_c = bT - 1;  // F(AT+1+i, BT-1)
         hcol[tid] = hc_c >= hc_r ? F[hc_r * ld + hc_c] : 0;
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int e = tid + u * kTileThreads;
-        Lt[(e & 63) * 64 + (e >> 6)] = lv[u];
-    }
+    // this thread holds L(8u + wave, lane), u = 0..7: eight consecutive words
+    *reinterpret_cast<int4*>(&Lp[lane * LS + 8 * wave]) = make_int4(lv[0], lv[1], lv[2], lv[3]);
+    *reinterpret_cast<int4*>(&Lp[lane * LS + 8 * wave + 4]) = make_int4(lv[4], lv[5], lv[6], lv[7]);
     if (it.nslot > 0) {  // hand the accumulator back zeroed for its next use
 #pragma unroll
-        for (int r = 0; r < 8; ++r) accp[r * 64] = 0;
+        for (int b = 0; b < 8; ++b) accp[b * 512] = 0;
     }
     __syncthreads();
 
     // ---- row words of tile (A, A) for the block pushes
     if constexpr (kBlockFR) {
         for (int x = tid; x < G * 64; x += kTileThreads) {
-            const int k = x >> 6, i = x & 63;
+            const int k = x >> 6, pos = x & 63;       // pos = 8g' + b'
+            const int r = (pos & 7) * 8 + (pos >> 3);  // row 8b' + g'
             const int top = k * Q;
             uint32_t h = 0;
             int base = 0;
-            if (top > i && top < T) {
-                base = Lt[top * 64 + i];
+            if (top > r && top < T) {
+                base = Lp[top * LS + pos];
 #pragma unroll
                 for (int p = 1; p <= M; ++p)
-                    h |= (uint32_t)(Lt[(top + p) * 64 + i] > Lt[(top + p - 1) * 64 + i]) << (p - 1);
+                    h |= (uint32_t)(Lp[(top + p) * LS + pos] > Lp[(top + p - 1) * LS + pos]) << (p - 1);
             }
             LW[x] = ((uint32_t)base << 16) | (h << M);
         }
     }
 
-    // ---- groups of the two end tiles C = A+1 and C = B-1
+    // column words of the end tiles at this lane's column (fixed for the tile)
+    uint32_t ecw[NE];
     if constexpr (kStageEdges) {
-        for (int e = 0; e < nedge; ++e) {
-            const uint32_t* eb = &EW[e * 3 * G * 64];
-            const uint32_t* eh = eb + G * 64;
-            const uint32_t* ec = eh + G * 64;
-#pragma unroll 2
-            for (int k = 0; k < G; ++k) {
-                const uint32_t cw = ec[k * 64 + j];
-                const uint32_t clo = cw & 0xffffu;
-                const int chi = (int)(cw >> 16);
-                const uint4 ba = *reinterpret_cast<const uint4*>(&eb[k * 64 + r0]);
-                const uint4 bb = *reinterpret_cast<const uint4*>(&eb[k * 64 + r0 + 4]);
-                const uint4 ha = *reinterpret_cast<const uint4*>(&eh[k * 64 + r0]);
-                const uint4 hb = *reinterpret_cast<const uint4*>(&eh[k * 64 + r0 + 4]);
-                const uint32_t bs[8] = {ba.x, ba.y, ba.z, ba.w, bb.x, bb.y, bb.z, bb.w};
-                const uint32_t hs[8] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w};
 #pragma unroll
-                for (int r = 0; r < 8; ++r) acc[r] = max(acc[r], (int)bs[r] + chi + (int)Rl[hs[r] + clo]);
-            }
-        }
+        for (int x = 0; x < NE; ++x) ecw[x] = EC[x * 64 + j];
+    }
+    // one end-tile lookup (edge e, group k) for row 8b + g
+    auto edge = [&](int x, int b) {
+        const uint2 rw = EB[x * 64 + 8 * b + g];
+        return (int)rw.x + (int)(ecw[x] >> 16) + (int)Rl[rw.y + (ecw[x] & 0xffffu)];
+    };
+
+    if constexpr (kStageEdges) {
+        // rows of block 7 take their end-tile groups here, the other blocks
+        // inside the row loop
+#pragma unroll
+        for (int x = 0; x < NE; ++x) acc[7] = max(acc[7], edge(x, 7));
     } else {
-        // rows r0..r0+7 of column j: the wave-uniform row-word path needs all
-        // lanes on the same rows, so go element by element through LDS-free
-        // global reads (q < 4 only)
+        // q < 4: the end tiles' words are read straight from memory
         for (int e = 0; e < nedge; ++e) {
             const int C = e == 0 ? A + 1 : B - 1;
-            const uint32_t* rb = f.RS + tile_index(f.NT, A, C - A) * RW;
-            const uint32_t* cs = f.CS + tile_index(f.NT, C, B - C) * SW;
+            const NF_GLOBAL uint32_t* rb = RSr + tile_index(f.NT, A, C - A) * RW;
+            const NF_GLOBAL uint32_t* cs = CSr + tile_index(f.NT, C, B - C) * SW;
             for (int k = 0; k < G; ++k) {
                 const uint32_t cw = cs[k * 64 + j];
                 const uint32_t clo = cw & 0xffffu;
                 const int chi = (int)(cw >> 16);
 #pragma unroll
-                for (int r = 0; r < 8; ++r)
-                    acc[r] = max(acc[r], (int)rb[k * 64 + r0 + r] + chi + (int)Rl[rb[G * 64 + k * 64 + r0 + r] + clo]);
+                for (int b = 0; b < 8; ++b) {
+                    const int r = 8 * b + g;
+                    acc[b] = max(acc[b], (int)rb[k * 64 + r] + chi + (int)Rl[rb[G * 64 + k * 64 + r] + clo]);
+                }
             }
         }
     }
@@ -413,64 +445,110 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
     uint32_t pmask = 0;
     if (wave == 0) {  // pairing masks of the slice-start columns, by ballot over rows
         const int cal = ca[lane];
+        int cbs[8];
 #pragma unroll
-        for (int gg = 0; gg < 8; ++gg) {
-            const unsigned long long m = __ballot(cal + (int)cb[gg * 8] == 3);
-            if (lane == 0) GM[gg] = m;
+        for (int gg = 0; gg < 8; ++gg) cbs[gg] = cb[gg * 8];
+        unsigned long long m[8];
+#pragma unroll
+        for (int gg = 0; gg < 8; ++gg) m[gg] = __ballot(cal + cbs[gg] == 3);
+        if (lane == 0) {
+#pragma unroll
+            for (int gg = 0; gg < 8; ++gg) GM[gg] = m[gg];
         }
     }
+    const int hrj = hrow[j];
+    int cai[8], hci[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int i = r0 + r;
-        if (i < T && j < T) {
-            const int bp = (ca[i] + cbj == 3) ? 1 : 0;
-            pmask |= (uint32_t)bp << r;
-            if (i == T - 1) acc[r] = max(acc[r], bp + hrow[j]);
-            else if (j == 0) acc[r] = max(acc[r], bp + hcol[i]);
-        }
+    for (int b = 0; b < 8; ++b) {
+        cai[b] = ca[8 * b + g];
+        hci[b] = hcol[8 * b + g];
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int i = 8 * b + g;
+        const int bp = (i < T && j < T && cai[b] + cbj == 3) ? 1 : 0;
+        pmask |= (uint32_t)bp << b;
+        const int halo = (i == T - 1) ? hrj : hci[b];  // the last row's partner first, then column 0's
+        if (i < T && j < T && (i == T - 1 || j == 0)) acc[b] = max(acc[b], bp + halo);
     }
 
+    // outputs: dense cells, row words (bases, then bits at + G*64), column
+    // words, written after the row loop (global address space: generic
+    // accesses also count against the LDS counter that barriers wait on)
+    const long long t_idx = tile_index(f.NT, A, d);
+    NF_GLOBAL int16_t* Fw = (NF_GLOBAL int16_t*)f.F;
+    NF_GLOBAL uint32_t* RSw = (NF_GLOBAL uint32_t*)(f.RS + t_idx * RW);
+    NF_GLOBAL uint32_t* CSw = (NF_GLOBAL uint32_t*)(f.CS + t_idx * SW);
+
     // ---- rows bottom-up.  Rows >= T (only when T < 64) are inert: their
-    // pushes are -inf in Lt and their pairing into row T-1 is skipped.
+    // pushes are -inf in Lp and their pairing into row T-1 is skipped.
     if (g == 7) Qs[1][j] = acc[7];  // row 63: Q complete (no row below)
+    // end-tile row words of the share of row (bb, r): groups x = r + 8m of
+    // block bb-1, loaded one row step ahead of their use
+    constexpr int kEPer = (NE + 7) / 8;
+    uint2 erw[kEPer];
+    auto fetch_edges = [&](int bb, int r) {
+#pragma unroll
+        for (int m = 0; m < kEPer; ++m) {
+            const int x = r + 8 * m;
+            erw[m] = (bb >= 1 && x < NE) ? EB[x * 64 + 8 * (bb - 1) + g] : make_uint2(0u, 0u);
+        }
+    };
+    if constexpr (kStageEdges) fetch_edges(7, 7);
     __syncthreads();
     const unsigned long long gmask = GM[g];
 
-#pragma unroll 1
+#pragma unroll
     for (int blk = 7; blk >= 0; --blk) {
 #pragma unroll
         for (int rr = 7; rr >= 0; --rr) {
             const int i = blk * 8 + rr;
-            // Q(i, 8g..8g+7); the pairing term of column 8g is added here
-            const int4 qa = *reinterpret_cast<const int4*>(&Qs[i & 1][r0]);
-            const int4 qb = *reinterpret_cast<const int4*>(&Qs[i & 1][r0 + 4]);
-            const int4 la = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0]);
-            const int4 lb = *reinterpret_cast<const int4*>(&Lt[i * 64 + r0 + 4]);
-            int q0 = qa.x;
-            if (i < T - 1 && g > 0) {
-                const int xl = Xs[(i + 1) * 64 + r0 - 1];  // X(i+1, 8g-1)
-                q0 = max(q0, (int)((gmask >> i) & 1u) + xl);
+            // ---- LDS loads of the row, issued together after the barrier:
+            // Q(i, 8g..8g+7), the pairing partner of column 8g, L(., i) for
+            // the pushes, and the end-tile words of this row's share of
+            // block blk-1
+            const int4 qa = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g]);
+            const int4 qb = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g + 4]);
+            int xl = kNeg;
+            if (i < T - 1) xl = Xs[(i + 1) * 64 + 8 * g - 1];  // X(i+1, 8g-1); unused for g = 0
+            int lp[8];
+            if constexpr (kBlockFR) {
+                lp[blk] = Lp[i * LS + 8 * g + blk];
+            } else {
+                const int4 la = *reinterpret_cast<const int4*>(&Lp[i * LS + 8 * g]);
+                const int4 lb = *reinterpret_cast<const int4*>(&Lp[i * LS + 8 * g + 4]);
+                lp[0] = la.x; lp[1] = la.y; lp[2] = la.z; lp[3] = la.w;
+                lp[4] = lb.x; lp[5] = lb.y; lp[6] = lb.z; lp[7] = lb.w;
             }
+            int ev = 0;  // best end-tile term of this row's share (words fetched a row ahead)
+            if constexpr (kStageEdges) {
+                if (blk >= 1) {
+#pragma unroll
+                    for (int m = 0; m < kEPer; ++m) {
+                        const int x = rr + 8 * m;
+                        if (x < NE)
+                            ev = max(ev, (int)erw[m].x + (int)(ecw[x] >> 16) + (int)Rl[erw[m].y + (ecw[x] & 0xffffu)]);
+                    }
+                }
+                fetch_edges(rr > 0 ? blk : blk - 1, rr > 0 ? rr - 1 : 7);
+            }
+            int q0 = qa.x;
+            if (i < T - 1 && g > 0) q0 = max(q0, (int)((gmask >> i) & 1u) + xl);
             // closure over j' in [8g, 8g+8), then across the 8 lane groups
             int p = max(max(q0 + ureg[0], qa.y + ureg[1]), max(qa.z + ureg[2], qa.w + ureg[3]));
             p = max(p, max(max(qb.x + ureg[4], qb.y + ureg[5]), max(qb.z + ureg[6], qb.w + ureg[7])));
             const int xi = max_over_groups(p);  // X(i, j)
-            if (g == 0) Xs[i * 64 + j] = xi;
-            // pushes: rows of this block above i, one split at a time (rows
-            // of other lanes' blocks above get the same exact terms, harmless)
-            {
-                const int lt[8] = {la.x, la.y, la.z, la.w, lb.x, lb.y, lb.z, lb.w};
-                if constexpr (kBlockFR) {
-#pragma unroll
-                    for (int r = 0; r < 8; ++r)
-                        if (r < rr) acc[r] = max(acc[r], lt[r] + xi);
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 8; ++r) acc[r] = max(acc[r], lt[r] + xi);
-                }
-            }
+            // pushes of row i: into row 8*blk+g (one split; -inf unless the row
+            // is above i), or for other q into every row above
             if constexpr (kBlockFR) {
-                if (rr == 0 && blk > 0 && g < blk) {
+                acc[blk] = max(acc[blk], lp[blk] + xi);
+            } else {
+#pragma unroll
+                for (int b = 0; b <= blk; ++b) acc[b] = max(acc[b], lp[b] + xi);
+            }
+            if (blk >= 1) acc[blk - 1] = max(acc[blk - 1], ev);
+            if constexpr (kBlockFR) {
+                if (rr == 0 && blk >= 1) {
                     // block blk finished: its q-groups into every row above it
 #pragma unroll
                     for (int gg = 0; gg < GPB; ++gg) {
@@ -484,16 +562,11 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
 #pragma unroll
                         for (int p2 = 1; p2 <= M; ++p2) cbits |= (uint32_t)(xs[p2 - 1] > xs[p2]) << (p2 - 1);
                         const uint32_t cw = ((uint32_t)xs[0] << 16) | cbits;
-                        const uint4 wa = *reinterpret_cast<const uint4*>(&LW[k * 64 + r0]);
-                        const uint4 wb = *reinterpret_cast<const uint4*>(&LW[k * 64 + r0 + 4]);
-                        acc[0] = max(acc[0], rlookup<Q>(Rl, wa.x, cw));
-                        acc[1] = max(acc[1], rlookup<Q>(Rl, wa.y, cw));
-                        acc[2] = max(acc[2], rlookup<Q>(Rl, wa.z, cw));
-                        acc[3] = max(acc[3], rlookup<Q>(Rl, wa.w, cw));
-                        acc[4] = max(acc[4], rlookup<Q>(Rl, wb.x, cw));
-                        acc[5] = max(acc[5], rlookup<Q>(Rl, wb.y, cw));
-                        acc[6] = max(acc[6], rlookup<Q>(Rl, wb.z, cw));
-                        acc[7] = max(acc[7], rlookup<Q>(Rl, wb.w, cw));
+                        const uint4 wa = *reinterpret_cast<const uint4*>(&LW[k * 64 + 8 * g]);
+                        const uint4 wb = *reinterpret_cast<const uint4*>(&LW[k * 64 + 8 * g + 4]);
+                        const uint32_t ws[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+#pragma unroll
+                        for (int b = 0; b < blk; ++b) acc[b] = max(acc[b], rlookup<Q>(Rl, ws[b], cw));
                     }
                 }
             }
@@ -501,23 +574,19 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
             // is the lane to the left; column 8w gets it from its readers)
             if (i >= 1) {
                 const int left = __builtin_amdgcn_update_dpp(kNeg, xi, 0x111, 0xF, 0xF, false);  // row_shr:1
-                const int gq = (rr > 0) ? blk : blk - 1;
-                const int slot = (rr > 0) ? rr - 1 : 7;
-                if (g == gq) {
-                    int qv = acc[slot];
-                    if (i < T && c > 0) qv = max(qv, (int)((pmask >> slot) & 1u) + left);
+                const int go = (i - 1) & 7, bo = (i - 1) >> 3;
+                if (g == go) {
+                    int qv = acc[bo];
+                    if (i < T && c > 0) qv = max(qv, (int)((pmask >> bo) & 1u) + left);
                     Qs[(i - 1) & 1][j] = qv;
                 }
             }
+            if (g == 0) Xs[i * 64 + j] = xi;
             __syncthreads();
         }
     }
 
     // ---- emit: dense cells, row words (ballot), column words
-    int16_t* Fw = f.F;
-    const long long t_idx = tile_index(f.NT, A, d);
-    uint32_t* RSw = f.RS + t_idx * RW;  // bases, then bits at + G*64
-    uint32_t* CSw = f.CS + t_idx * SW;
     {
         const int wv = tid >> 6, ln = tid & 63;  // row-major view: wave -> 8 rows, lane -> column
 #pragma unroll
@@ -741,31 +810,41 @@ __global__ void k_expand(const int16_t* __restrict__ F, int ld, int n, int16_t* 
     }
 }
 
-template <int Q>
-hipError_t launch_q(int which, const void* items, int nitems, const uint8_t* R, hipStream_t s)
+// Launch on stream s; with events, the dispatch itself records e0 when the
+// kernel starts and e1 when it ends (kernel-only durations for profiling).
+template <class K, class... Args>
+hipError_t launch_k(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args)
 {
-    if (nitems <= 0) return hipSuccess;
-    dim3 grid(nitems), block(kThreads);
-    if (which == 0)
-        hipLaunchKernelGGL(k_diag<Q>, grid, block, 0, s, (const TileWork*)items);
-    else if (which == 1)
-        hipLaunchKernelGGL(k_tile<Q>, grid, dim3(kTileThreads), 0, s, (const TileWork*)items, R);
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, args...);
     else
-        hipLaunchKernelGGL(k_between<Q>, grid, block, 0, s, (const BetweenWork*)items, R);
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
     return hipGetLastError();
 }
 
-hipError_t dispatch(int q, int which, const void* items, int nitems, const uint8_t* R, hipStream_t s)
+template <int Q>
+hipError_t launch_q(int which, const void* items, int nitems, const uint8_t* R, hipStream_t s, hipEvent_t e0,
+                    hipEvent_t e1)
+{
+    if (nitems <= 0) return hipSuccess;
+    dim3 grid(nitems), block(kThreads);
+    if (which == 0) return launch_k(k_diag<Q>, grid, block, s, e0, e1, (const TileWork*)items);
+    if (which == 1) return launch_k(k_tile<Q>, grid, dim3(kTileThreads), s, e0, e1, (const TileWork*)items, R);
+    return launch_k(k_between<Q>, grid, block, s, e0, e1, (const BetweenWork*)items, R);
+}
+
+hipError_t dispatch(int q, int which, const void* items, int nitems, const uint8_t* R, hipStream_t s, hipEvent_t e0,
+                    hipEvent_t e1)
 {
     switch (q) {
-    case 1: return launch_q<1>(which, items, nitems, R, s);
-    case 2: return launch_q<2>(which, items, nitems, R, s);
-    case 3: return launch_q<3>(which, items, nitems, R, s);
-    case 4: return launch_q<4>(which, items, nitems, R, s);
-    case 5: return launch_q<5>(which, items, nitems, R, s);
-    case 6: return launch_q<6>(which, items, nitems, R, s);
-    case 7: return launch_q<7>(which, items, nitems, R, s);
-    case 8: return launch_q<8>(which, items, nitems, R, s);
+    case 1: return launch_q<1>(which, items, nitems, R, s, e0, e1);
+    case 2: return launch_q<2>(which, items, nitems, R, s, e0, e1);
+    case 3: return launch_q<3>(which, items, nitems, R, s, e0, e1);
+    case 4: return launch_q<4>(which, items, nitems, R, s, e0, e1);
+    case 5: return launch_q<5>(which, items, nitems, R, s, e0, e1);
+    case 6: return launch_q<6>(which, items, nitems, R, s, e0, e1);
+    case 7: return launch_q<7>(which, items, nitems, R, s, e0, e1);
+    case 8: return launch_q<8>(which, items, nitems, R, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -787,19 +866,21 @@ hipError_t launch_copy_codes(const uint8_t* src, int n, uint8_t* dst, int padded
     return hipGetLastError();
 }
 
-hipError_t launch_diag(int q, const TileWork* items, int nitems, hipStream_t s)
+hipError_t launch_diag(int q, const TileWork* items, int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    return dispatch(q, 0, items, nitems, nullptr, s);
+    return dispatch(q, 0, items, nitems, nullptr, s, e0, e1);
 }
 
-hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, hipStream_t s)
+hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, hipStream_t s, hipEvent_t e0,
+                       hipEvent_t e1)
 {
-    return dispatch(q, 1, items, nitems, R, s);
+    return dispatch(q, 1, items, nitems, R, s, e0, e1);
 }
 
-hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, hipStream_t s)
+hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, hipStream_t s, hipEvent_t e0,
+                          hipEvent_t e1)
 {
-    return dispatch(q, 2, items, nitems, R, s);
+    return dispatch(q, 2, items, nitems, R, s, e0, e1);
 }
 
 hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, const int32_t* err, hipStream_t s)
@@ -819,10 +900,9 @@ hipError_t launch_zero(int32_t* p, long long count, hipStream_t s)
 namespace {
 template <int Q>
 hipError_t queue_q(const QItem* items, int nitems, const QFold* folds, const uint8_t* R, int* head, int* err,
-                   int blocks, hipStream_t s)
+                   int blocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    hipLaunchKernelGGL(k_queue<Q>, dim3(blocks), dim3(kTileThreads), 0, s, items, nitems, folds, R, head, err);
-    return hipGetLastError();
+    return launch_k(k_queue<Q>, dim3(blocks), dim3(kTileThreads), s, e0, e1, items, nitems, folds, R, head, err);
 }
 template <int Q>
 int occupancy_q()
@@ -838,44 +918,44 @@ int occupancy_q()
 
 namespace {
 template <int Q>
-hipError_t stage_q(const TileWork* t, int nt, const BetweenWork* b, int nb, const uint8_t* R, hipStream_t s)
+hipError_t stage_q(const TileWork* t, int nt, const BetweenWork* b, int nb, const uint8_t* R, hipStream_t s,
+                   hipEvent_t e0, hipEvent_t e1)
 {
-    hipLaunchKernelGGL(k_stage<Q>, dim3(nt + nb), dim3(kTileThreads), 0, s, t, nt, b, R);
-    return hipGetLastError();
+    return launch_k(k_stage<Q>, dim3(nt + nb), dim3(kTileThreads), s, e0, e1, t, nt, b, R);
 }
 }  // namespace
 
 hipError_t launch_stage(int q, const TileWork* titems, int ntile, const BetweenWork* bitems, int nbtw,
-                        const uint8_t* R, hipStream_t s)
+                        const uint8_t* R, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (ntile + nbtw <= 0) return hipSuccess;
     switch (q) {
-    case 1: return stage_q<1>(titems, ntile, bitems, nbtw, R, s);
-    case 2: return stage_q<2>(titems, ntile, bitems, nbtw, R, s);
-    case 3: return stage_q<3>(titems, ntile, bitems, nbtw, R, s);
-    case 4: return stage_q<4>(titems, ntile, bitems, nbtw, R, s);
-    case 5: return stage_q<5>(titems, ntile, bitems, nbtw, R, s);
-    case 6: return stage_q<6>(titems, ntile, bitems, nbtw, R, s);
-    case 7: return stage_q<7>(titems, ntile, bitems, nbtw, R, s);
-    case 8: return stage_q<8>(titems, ntile, bitems, nbtw, R, s);
+    case 1: return stage_q<1>(titems, ntile, bitems, nbtw, R, s, e0, e1);
+    case 2: return stage_q<2>(titems, ntile, bitems, nbtw, R, s, e0, e1);
+    case 3: return stage_q<3>(titems, ntile, bitems, nbtw, R, s, e0, e1);
+    case 4: return stage_q<4>(titems, ntile, bitems, nbtw, R, s, e0, e1);
+    case 5: return stage_q<5>(titems, ntile, bitems, nbtw, R, s, e0, e1);
+    case 6: return stage_q<6>(titems, ntile, bitems, nbtw, R, s, e0, e1);
+    case 7: return stage_q<7>(titems, ntile, bitems, nbtw, R, s, e0, e1);
+    case 8: return stage_q<8>(titems, ntile, bitems, nbtw, R, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_queue(int q, const QItem* items, int nitems, const QFold* folds, const uint8_t* R, int* head,
-                        int* err, int blocks, hipStream_t s)
+                        int* err, int blocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (nitems <= 0) return hipSuccess;
     if (blocks <= 0) return hipErrorInvalidValue;
     switch (q) {
-    case 1: return queue_q<1>(items, nitems, folds, R, head, err, blocks, s);
-    case 2: return queue_q<2>(items, nitems, folds, R, head, err, blocks, s);
-    case 3: return queue_q<3>(items, nitems, folds, R, head, err, blocks, s);
-    case 4: return queue_q<4>(items, nitems, folds, R, head, err, blocks, s);
-    case 5: return queue_q<5>(items, nitems, folds, R, head, err, blocks, s);
-    case 6: return queue_q<6>(items, nitems, folds, R, head, err, blocks, s);
-    case 7: return queue_q<7>(items, nitems, folds, R, head, err, blocks, s);
-    case 8: return queue_q<8>(items, nitems, folds, R, head, err, blocks, s);
+    case 1: return queue_q<1>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
+    case 2: return queue_q<2>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
+    case 3: return queue_q<3>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
+    case 4: return queue_q<4>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
+    case 5: return queue_q<5>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
+    case 6: return queue_q<6>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
+    case 7: return queue_q<7>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
+    case 8: return queue_q<8>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }

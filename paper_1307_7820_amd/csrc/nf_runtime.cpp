@@ -620,6 +620,14 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
     };
     struct Rec { int kind; hipEvent_t a, b; double lk, sp, cells; };
     std::vector<Rec> recs;
+    // every timed launch gets its own event pair, recorded by the dispatch
+    // itself at kernel start and end
+    auto pair = [&](hipEvent_t& e0, hipEvent_t& e1) {
+        e0 = fresh();
+        e1 = fresh();
+        return e0 && e1;
+    };
+    hipEvent_t a = nullptr, b = nullptr;
     if (p.mode == kModeQueue) {
         double lk = 0, sp = diag_sp, cells = diag_cells;
         for (int sg = 0; sg < sc.stages; ++sg) {
@@ -632,58 +640,36 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
         const int blocks = std::max(1, std::min(p.nqitems, c.queue_blocks[p.q] * c.num_cu));
         for (int r = 0; r < reps; ++r) {
             HIPCHK(launch_zero(st, p.qstate_ints, s));
-            hipEvent_t a = fresh(), b = fresh();
-            HIPCHK(hipEventRecord(a, s));
+            if (!pair(a, b)) return fail(NF_E_DEVICE, "event creation failed");
             HIPCHK(launch_queue(p.q, (const QItem*)p.d_qitems.p, p.nqitems, (const QFold*)p.d_qfolds.p, R, st, st + 1,
-                                blocks, s));
-            HIPCHK(hipEventRecord(b, s));
+                                blocks, s, a, b));
             recs.push_back({3, a, b, lk, sp, cells});
             HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, st + 1, s));
         }
-    } else if (p.mode == kModeFused) {
-        for (int r = 0; r < reps; ++r) {
-            hipEvent_t a = fresh(), b = fresh();
-            HIPCHK(hipEventRecord(a, s));
-            HIPCHK(launch_diag(p.q, (const TileWork*)p.d_diag.p, (int)sc.diag.size(), s));
-            if (sc.btw_cnt[0] > 0)
-                HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[0], sc.btw_cnt[0], R, s));
-            HIPCHK(hipEventRecord(b, s));
-            recs.push_back({0, a, b, btw_lk[0], diag_sp, diag_cells});
-            for (int sg = 1; sg < sc.stages; ++sg) {
-                if (sc.tile_cnt[sg] + sc.btw_cnt[sg] == 0) continue;
-                a = fresh();
-                b = fresh();
-                HIPCHK(hipEventRecord(a, s));
-                HIPCHK(launch_stage(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg],
-                                    (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R, s));
-                HIPCHK(hipEventRecord(b, s));
-                recs.push_back({4, a, b, tile_lk[sg] + btw_lk[sg], tile_sp[sg], tile_cells[sg]});
-            }
-            HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, nullptr, s));
-        }
     } else {
+        const bool fused = p.mode == kModeFused;
         for (int r = 0; r < reps; ++r) {
-            hipEvent_t a = fresh(), b = fresh();
-            HIPCHK(hipEventRecord(a, s));
-            HIPCHK(launch_diag(p.q, (const TileWork*)p.d_diag.p, (int)sc.diag.size(), s));
-            HIPCHK(hipEventRecord(b, s));
+            if (!pair(a, b)) return fail(NF_E_DEVICE, "event creation failed");
+            HIPCHK(launch_diag(p.q, (const TileWork*)p.d_diag.p, (int)sc.diag.size(), s, a, b));
             recs.push_back({0, a, b, 0.0, diag_sp, diag_cells});
             for (int sg = 0; sg < sc.stages; ++sg) {
+                const TileWork* tw = (const TileWork*)p.d_tile.p + sc.tile_off[sg];
+                const BetweenWork* bw = (const BetweenWork*)p.d_btw.p + sc.btw_off[sg];
+                if (fused && sg >= 1) {
+                    if (sc.tile_cnt[sg] + sc.btw_cnt[sg] == 0) continue;
+                    if (!pair(a, b)) return fail(NF_E_DEVICE, "event creation failed");
+                    HIPCHK(launch_stage(p.q, tw, sc.tile_cnt[sg], bw, sc.btw_cnt[sg], R, s, a, b));
+                    recs.push_back({4, a, b, tile_lk[sg] + btw_lk[sg], tile_sp[sg], tile_cells[sg]});
+                    continue;
+                }
                 if (sg >= 1 && sc.tile_cnt[sg] > 0) {
-                    a = fresh();
-                    b = fresh();
-                    HIPCHK(hipEventRecord(a, s));
-                    HIPCHK(launch_tile(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R, s));
-                    HIPCHK(hipEventRecord(b, s));
+                    if (!pair(a, b)) return fail(NF_E_DEVICE, "event creation failed");
+                    HIPCHK(launch_tile(p.q, tw, sc.tile_cnt[sg], R, s, a, b));
                     recs.push_back({1, a, b, tile_lk[sg], tile_sp[sg], tile_cells[sg]});
                 }
                 if (sc.btw_cnt[sg] > 0) {
-                    a = fresh();
-                    b = fresh();
-                    HIPCHK(hipEventRecord(a, s));
-                    HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R,
-                                          s));
-                    HIPCHK(hipEventRecord(b, s));
+                    if (!pair(a, b)) return fail(NF_E_DEVICE, "event creation failed");
+                    HIPCHK(launch_between(p.q, bw, sc.btw_cnt[sg], R, s, a, b));
                     recs.push_back({2, a, b, btw_lk[sg], 0.0, 0.0});
                 }
             }
@@ -693,7 +679,6 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
     HIPCHK(hipStreamSynchronize(s));
     for (auto& rc2 : recs) {
         float ms = 0;
-        if (!rc2.a || !rc2.b) return fail(NF_E_DEVICE, "event creation failed");
         HIPCHK(hipEventElapsedTime(&ms, rc2.a, rc2.b));
         out->launches[rc2.kind] += 1;
         out->ms[rc2.kind] += ms;
