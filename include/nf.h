@@ -92,17 +92,13 @@ int nf_copy_R(int q, uint8_t* out, size_t cap);
  * workspace: when a step holds few tiles (one fold up to n of about 13000)
  * each step is one launch holding the finishes of diagonal s and the
  * between-group chunks of diagonal s+1; otherwise the two kinds run as
- * separate launches on two streams.  NF_MODE=staged|fused|queue forces one;
- * "queue" is one persistent launch draining a dependency-ordered work queue
- * (per-tile counters in device memory), where a device-side wait longer than
- * 4 s makes the call fail with NF_E_DEVICE (the table is then invalid). */
+ * separate launches on two streams.  NF_MODE=staged|fused forces one. */
 int nf_fold(const char* seq, int n, int q, int16_t* S_out);
 
 /* ---- Single fold (device buffers, asynchronous on a HIP stream) ----
  * d_codes: n device bytes, base codes A=0, C=1, G=2, U=3 (other values give
  *          unspecified scores but never access memory out of bounds).
- * d_score: device int32 that receives D(1,n) (may be NULL); -1 when a
- *          device-side dependency wait timed out (see nf_fold).
+ * d_score: device int32 that receives D(1,n) (may be NULL).
  * d_S:     device int16 n*n table, layout above (may be NULL; when set the
  *          lower triangle is written as 0).
  * stream:  hipStream_t passed as void* (NULL = the null stream).
@@ -114,9 +110,7 @@ int nf_fold_dev(const uint8_t* d_codes, int n, int q, int32_t* d_score, int16_t*
 /* ---- Batched folds: one packed wavefront over many sequences ----
  * A prepared batch uploads the codes of all sequences once, builds the packed
  * per-diagonal work lists of all of them and captures the whole fill as one
- * HIP graph (execution as for nf_fold; with NF_MODE=queue, one persistent
- * launch over the tiles of every sequence).  nf_batch_scores returns
- * NF_E_DEVICE when a device-side dependency wait timed out.
+ * HIP graph (execution as for nf_fold).
  * Handles are opaque; a handle must only be used from one thread at a time. */
 typedef struct nf_batch nf_batch;
 
@@ -196,20 +190,19 @@ int nf_autotune(int n, int qmin, int qmax, int reps);
  * the kernel starts and ends (hipExtLaunchKernelGGL), and the durations are
  * summed per kernel class k:
  * 0 = main-diagonal tiles, 1 = tile finish, 2 = between-group lookups (the
- * launches of the staged execution), 3 = the persistent fill (the whole table
- * in one launch), 4 = one fused step (finishes of a diagonal and the
- * between-group chunks of the next); the fill runs in the execution its
- * workspace uses (see nf_fold).  For every class:
+ * launches of the staged execution), 3 = one fused step (finishes of a
+ * diagonal and the between-group chunks of the next); the fill runs in the
+ * execution its workspace uses (see nf_fold).  For every class:
  * lookups[k] counts the Four-Russians steps of Eq. 3 on table cells (padding
  * excluded), splits[k] the terms of Eq. 1 evaluated one by one inside tiles
  * (split points within a tile's own rows or columns, plus the pairing term),
  * cells[k] the table cells finished.  Synchronous. */
 typedef struct {
-    int64_t launches[5];
-    double ms[5];
-    double lookups[5];
-    double splits[5];
-    double cells[5];
+    int64_t launches[4];
+    double ms[4];
+    double lookups[4];
+    double splits[4];
+    double cells[4];
     int q, tile, tiles_per_side, stages;
 } nf_kernel_profile_t;
 int nf_profile_fold(const uint8_t* d_codes, int n, int q, int reps, void* stream, nf_kernel_profile_t* out);

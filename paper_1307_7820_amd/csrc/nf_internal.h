@@ -96,40 +96,6 @@ static_assert(sizeof(BetweenWork) == 80, "BetweenWork layout");
 hipError_t launch_stage(int q, const TileWork* titems, int ntile, const BetweenWork* bitems, int nbtw,
                         const uint8_t* R, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
-// Work queue of the persistent fill (one launch per plan run).  Items are
-// claimed in array order through an atomic head counter and each item only
-// waits for items placed before it, so every wait ends: the items it waits
-// for were claimed earlier by workgroups that are already running.
-//   kind kQDiag:    tile (A, A)
-//   kind kQFinish:  finish of tile (A, A+d); aux = number of between chunks
-//   kind kQBetween: between chunk of tile (A, A+d) over C in [c0, c1);
-//                   aux != 0 when the tile has several chunks (atomic max)
-// Per fold, tile (A, A+d) owns accumulator 2A + (d & 1); a between chunk
-// also waits for tile (A, A+d-2), the previous reader of that accumulator.
-enum { kQDiag = 0, kQFinish = 1, kQBetween = 2 };
-struct QItem {
-    int kind, fold, A, d, c0, c1, aux, pad;
-};
-struct QFold {
-    FoldDesc f;
-    int32_t* acc;   // 2*NT accumulators of 64x64 int32, zero between runs
-    int32_t* done;  // per tile (diagonal-major index): 1 once its cells and words are written
-    int32_t* bcnt;  // per tile: between chunks already folded into its accumulator
-    int32_t* pad;
-};
-static_assert(sizeof(QItem) == 32, "QItem layout");
-static_assert(sizeof(QFold) == 80, "QFold layout");
-
-// Persistent fill: `blocks` workgroups drain items[0..nitems); head and err
-// (device ints) and every done/bcnt counter must be zero at launch.  err is
-// set when a dependency wait exceeds its time limit (the run is then invalid).
-hipError_t launch_queue(int q, const QItem* items, int nitems, const QFold* folds, const uint8_t* R, int* head,
-                        int* err, int blocks, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-// Resident workgroups per CU of the persistent fill for q (0 on error).
-int queue_blocks_per_cu(int q);
-// Zero `count` ints at p (a fill kernel: safe inside captured graphs).
-hipError_t launch_zero(int32_t* p, long long count, hipStream_t s);
-
 hipError_t launch_precompute_R(int q, uint8_t* R, hipStream_t s);
 hipError_t launch_copy_codes(const uint8_t* src, int n, uint8_t* dst, int padded, hipStream_t s);
 // With events e0/e1 the dispatch records the kernel's own start and end.
@@ -139,8 +105,8 @@ hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* 
                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-// scores[f] = F(0, n_f); -1 for every fold when err is non-null and set.
-hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, const int32_t* err, hipStream_t s);
+// scores[f] = F(0, n_f)
+hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s);
 hipError_t launch_expand(const int16_t* F, int ld, int n, int16_t* S, hipStream_t s);
 
 }  // namespace nf

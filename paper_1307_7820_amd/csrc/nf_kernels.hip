@@ -223,6 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_between(const BetweenWork* __restr
 // C = B-1) for the rows of block b-1 are looked up while block b is closed,
 // a few per row, in the slack of the row steps.
 constexpr int kTileThreads = 512;
+static_assert(kTileThreads == 512, "the tile finish maps 8 wavefronts onto 8 column slices");
 constexpr int kNeg = -(1 << 20);  // stands for minus infinity; sums stay far from overflow
 
 template <int Q>
@@ -234,7 +235,7 @@ __device__ __forceinline__ int rlookup(const uint8_t* Rl, uint32_t rw, uint32_t 
 // max of v over the 8 lanes l ^ {8, 16, 32} (lanes 8g + c, g = 0..7)
 __device__ __forceinline__ int max_over_groups(int v)
 {
-    v = max(v, __builtin_amdgcn_update_dpp(kNeg, v, 0x128, 0xF, 0xF, false));  // row_ror:8 = lane ^ 8
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true));  // row_ror:8 = lane ^ 8 (every lane valid)
     // the swaps return unsigned words: compare them as signed (-inf is negative)
     auto p16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);           // {v[l], v[l ^ 16]}
     v = max((int)p16[0], (int)p16[1]);
@@ -262,13 +263,15 @@ struct TileLds {
     unsigned long long GM[8];  // GM[g] bit i: pairing of (row i, column 8g)
 };
 
-// The finish of one tile by kTileThreads threads.  wait_pre() runs before
+// The finish of one tile by kTileThreads threads.  With kLoadR the finish
+// copies R from Rg (global) into Rl itself; otherwise Rl already holds it.
+// wait_pre() runs before
 // the loads that need the main-diagonal tiles (A, A) and (B, B); wait_main()
 // before the loads that need the tiles of diagonal d-1 and the between-group
 // maxima.  Both are collective (every thread calls them).
-template <int Q, class Pre, class Main>
-__device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl, TileLds<Q>& s, Pre&& wait_pre,
-                                          Main&& wait_main)
+template <int Q, bool kLoadR, class Pre, class Main>
+__device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const uint8_t* Rg, TileLds<Q>& s,
+                                          Pre&& wait_pre, Main&& wait_main)
 {
     constexpr int M = Q - 1;
     constexpr int G = groups_per_tile(Q);
@@ -307,8 +310,28 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
     const NF_GLOBAL uint32_t* CSr = (const NF_GLOBAL uint32_t*)f.CS;
     const int nedge = d >= 3 ? 2 : (d == 2 ? 1 : 0);
 
-    // ---- prologue, part 1: L, U and the codes
+    // ---- prologue.  Every global load is issued before the first LDS store
+    // (an LDS store of loaded data waits on the load counter, which drains in
+    // order), so the tile pays about one memory round trip here.
+    // part 1: R (when loading it), L, U and the codes
     wait_pre();
+    constexpr int RSZ = 1 << (2 * M);
+    uint8_t rbyte = 0;
+    if constexpr (kLoadR) {
+        if constexpr (RSZ >= 16) {
+            // R goes global -> LDS by DMA (no registers, no LDS store): lane l
+            // of a wave lands at the wave's base + 16 l
+#pragma unroll
+            for (int u = 0; u < (RSZ + kTileThreads * 16 - 1) / (kTileThreads * 16); ++u) {
+                const int base = (u * kTileThreads + wave * 64) * 16;  // wave-uniform
+                if (base < RSZ)
+                    __builtin_amdgcn_global_load_lds((const NF_GLOBAL void*)(Rg + base + lane * 16),
+                                                     (__attribute__((address_space(3))) void*)(Rl + base), 16, 0, 0);
+            }
+        } else {
+            rbyte = ((const NF_GLOBAL uint8_t*)Rg)[min(tid, RSZ - 1)];
+        }
+    }
     int lv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -322,12 +345,13 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
         const int jp = 8 * g + t;
         ureg[t] = (jp <= j && j < T) ? (int)F[(bT + jp) * ld + bT + j] : kNeg;
     }
+    uint8_t cda = 0, cdb = 0;
     if (tid < 64) {
-        ca[tid] = codes[aT + tid];      // S_{a+1}, a = AT + i
-        cb[tid] = codes[bT + tid - 1];  // S_b,     b = BT + j  (BT >= 1)
+        cda = codes[aT + tid];      // S_{a+1}, a = AT + i
+        cdb = codes[bT + tid - 1];  // S_b,     b = BT + j  (BT >= 1)
     }
 
-    // ---- prologue, part 2: the between maxima, the end tiles and the halo
+    // part 2: the between maxima, the end tiles and the halo
     wait_main();
     int acc[8];  // acc[b]: row 8b + g, column j
     NF_GLOBAL int32_t* accp = (NF_GLOBAL int32_t*)(it.acc + g * 64 + j);
@@ -338,14 +362,14 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[b] = 0;
     }
+    // edge e: C = A+1 (e = 0) and C = B-1 (e = 1); {base, bits} per row of
+    // tile (A, C), column words of tile (C, B).  An end tile that does not
+    // exist (e >= nedge) gets zero words: its lookups then give 0, which no
+    // accumulator is below, so every lookup can run unguarded.  (The loads
+    // stay inside the fold's tile arrays either way.)
+    constexpr int kIter = kStageEdges ? (2 * G * 64 + kTileThreads - 1) / kTileThreads : 1;
+    uint32_t rb[kIter], rh[kIter], cw[kIter];
     if constexpr (kStageEdges) {
-        // edge e: C = A+1 (e = 0) and C = B-1 (e = 1); {base, bits} per row
-        // of tile (A, C), column words of tile (C, B).  An end tile that does
-        // not exist (e >= nedge) gets zero words: its lookups then give 0,
-        // which no accumulator is below, so every lookup can run unguarded.
-        // (The loads stay inside the fold's tile arrays either way.)
-        constexpr int kIter = (2 * G * 64 + kTileThreads - 1) / kTileThreads;
-        uint32_t rb[kIter], rh[kIter], cw[kIter];
 #pragma unroll
         for (int u = 0; u < kIter; ++u) {
             const int x = tid + u * kTileThreads;
@@ -360,6 +384,24 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
                 cw[u] = CSr[tile_index(f.NT, C, B - C) * SW + k * 64 + r];
             }
         }
+    }
+    int hrv = 0, hcv = 0;
+    if (tid < T) {
+        const int hr_r = aT + T, hr_c = bT - 1 + tid;  // F((A+1)T, BT-1+j)
+        if (hr_c >= hr_r) hrv = F[hr_r * ld + hr_c];
+        const int hc_r = aT + 1 + tid, hc_c = bT - 1;  // F(AT+1+i, BT-1)
+        if (hc_c >= hc_r) hcv = F[hc_r * ld + hc_c];
+    }
+
+    // stores
+    if constexpr (kLoadR && RSZ < 16) {
+        if (tid < RSZ) Rl[tid] = rbyte;
+    }
+    if (tid < 64) {
+        ca[tid] = cda;
+        cb[tid] = cdb;
+    }
+    if constexpr (kStageEdges) {
 #pragma unroll
         for (int u = 0; u < kIter; ++u) {
             const int x = tid + u * kTileThreads;
@@ -371,10 +413,8 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
         }
     }
     if (tid < T) {
-        const int hr_r = aT + T, hr_c = bT - 1 + tid;  // F((A+1)T, BT-1+j)
-        hrow[tid] = hr_c >= hr_r ? F[hr_r * ld + hr_c] : 0;
-        const int hc_r = aT + 1 + tid, hc_c = bT - 1;  // F(AT+1+i, BT-1)
-        hcol[tid] = hc_c >= hc_r ? F[hc_r * ld + hc_c] : 0;
+        hrow[tid] = hrv;
+        hcol[tid] = hcv;
     }
     // this thread holds L(8u + wave, lane), u = 0..7: eight consecutive words
     *reinterpret_cast<int4*>(&Lp[lane * LS + 8 * wave]) = make_int4(lv[0], lv[1], lv[2], lv[3]);
@@ -383,6 +423,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
 #pragma unroll
         for (int b = 0; b < 8; ++b) accp[b * 512] = 0;
     }
+    if constexpr (kLoadR) __builtin_amdgcn_s_waitcnt(0);  // the R transfer (vector memory counter) is done
     __syncthreads();
 
     // ---- row words of tile (A, A) for the block pushes
@@ -443,18 +484,9 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
     // outside the tile (last row, first column) come from the halo
     const int cbj = cb[j];
     uint32_t pmask = 0;
-    if (wave == 0) {  // pairing masks of the slice-start columns, by ballot over rows
-        const int cal = ca[lane];
-        int cbs[8];
-#pragma unroll
-        for (int gg = 0; gg < 8; ++gg) cbs[gg] = cb[gg * 8];
-        unsigned long long m[8];
-#pragma unroll
-        for (int gg = 0; gg < 8; ++gg) m[gg] = __ballot(cal + cbs[gg] == 3);
-        if (lane == 0) {
-#pragma unroll
-            for (int gg = 0; gg < 8; ++gg) GM[gg] = m[gg];
-        }
+    {  // pairing mask of slice-start column 8*wave, by ballot over rows
+        const unsigned long long m = __ballot(ca[lane] + (int)cb[wave * 8] == 3);
+        if (lane == 0) GM[wave] = m;
     }
     const int hrj = hrow[j];
     int cai[8], hci[8];
@@ -588,15 +620,21 @@ __device__ __forceinline__ void tile_body(const TileWork& it, const uint8_t* Rl,
 
     // ---- emit: dense cells, row words (ballot), column words
     {
-        const int wv = tid >> 6, ln = tid & 63;  // row-major view: wave -> 8 rows, lane -> column
+        const int wv = wave, ln = lane;  // row-major view: wave -> 8 rows, lane -> column
+        int xv[8], xlft[8];  // every LDS read first: X(i, ln) and X(i, ln-1)
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int i = wv * 8 + r;
+            xv[r] = Xs[i * 64 + ln];
+            xlft[r] = Xs[i * 64 + max(ln - 1, 0)];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int i = wv * 8 + r;
+            const int v = xv[r];
             if (i < T) {
-                const int v = Xs[i * 64 + ln];
                 if (ln < T) Fw[(aT + i) * ld + bT + ln] = (int16_t)v;
-                const int lft = __shfl_up(v, 1);
-                const unsigned long long diff = __ballot(ln > 0 && ln < T && v > lft);
+                const unsigned long long diff = __ballot(ln > 0 && ln < T && v > xlft[r]);
                 if (ln < T && (ln % Q) == 0) {
                     uint32_t h = 0;
                     if constexpr (M > 0) h = (uint32_t)(diff >> (ln + 1)) & ((1u << M) - 1u);
@@ -633,8 +671,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
     constexpr int RSZ = 1 << (2 * (Q - 1));
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
     __shared__ __align__(16) TileLds<Q> s;
-    load_R<RSZ>(Rl, Rg, kTileThreads);  // read after the first barrier of the body
-    tile_body<Q>(items[blockIdx.x], Rl, s, [] {}, [] {});
+    tile_body<Q, true>(items[blockIdx.x], Rl, Rg, s, [] {}, [] {});
 }
 
 // One wavefront step in one launch: workgroups [0, ntile) finish the tiles
@@ -649,11 +686,11 @@ __global__ __launch_bounds__(kTileThreads) void k_stage(const TileWork* __restri
     constexpr int kRows = 64 / (kTileThreads / 64);
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
     __shared__ __align__(16) TileLds<Q> s;
-    load_R<RSZ>(Rl, Rg, kTileThreads);  // read after the first barrier of either body
     const int b = blockIdx.x;
     if (b < ntile) {
-        tile_body<Q>(titems[b], Rl, s, [] {}, [] {});
+        tile_body<Q, true>(titems[b], Rl, Rg, s, [] {}, [] {});
     } else {
+        load_R<RSZ>(Rl, Rg, kTileThreads);
         __syncthreads();
         const BetweenWork& it = bitems[b - ntile];
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -661,139 +698,10 @@ __global__ __launch_bounds__(kTileThreads) void k_stage(const TileWork* __restri
     }
 }
 
-// ---- persistent fill
-
-// Dependency waits of the persistent fill.  One thread polls the counters
-// (agent-scope atomic loads) until every one reaches its target, then an
-// agent-scope acquire makes the producers' data visible to the workgroup;
-// the barrier releases the other threads.  The wait gives up after
-// kWaitTicks of the 100 MHz constant clock, or as soon as any workgroup has
-// given up, and flags err: every wave always gets past it.
-constexpr long long kWaitTicks = 400000000;  // 4 s
-constexpr int kQueueRowsPerWave = 64 / (kTileThreads / 64);  // between rows per wave
-
-__device__ __forceinline__ int ld_agent(const int32_t* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void wait_ge(const int32_t* p0, int v0, const int32_t* p1, int v1, const int32_t* p2,
-                                        int v2, int32_t* err)
-{
-    if (threadIdx.x == 0) {
-        const long long t0 = (long long)wall_clock64();
-        for (;;) {
-            const bool ok = (!p0 || ld_agent(p0) >= v0) && (!p1 || ld_agent(p1) >= v1) && (!p2 || ld_agent(p2) >= v2);
-            if (ok || ld_agent(err) != 0) break;
-            if ((long long)wall_clock64() - t0 > kWaitTicks) {
-                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-}
-
-// Publish the workgroup's results: every wave waits for its own stores and
-// atomics to complete, then one thread writes the L2 back to memory
-// (agent-scope release) and bumps the counter.
-__device__ __forceinline__ void signal_add(int32_t* p)
-{
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-template <int Q>
-union QueueLds {
-    TileLds<Q> t;
-    DiagLds dg;
-};
-
-template <int Q>
-__global__ __launch_bounds__(kTileThreads, 4) void k_queue(const QItem* __restrict__ items, int nitems,
-                                                        const QFold* __restrict__ folds,
-                                                        const uint8_t* __restrict__ Rg, int32_t* head, int32_t* err)
-{
-    constexpr int RSZ = 1 << (2 * (Q - 1));
-    __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
-    __shared__ __align__(16) QueueLds<Q> u;
-    __shared__ int s_item;
-    const int tid = threadIdx.x;
-    load_R<RSZ>(Rl, Rg, kTileThreads);  // read after the first barrier below
-
-    for (;;) {
-        __syncthreads();  // every wave is done with the previous item's LDS
-        if (tid == 0) s_item = atomicAdd(head, 1);
-        __syncthreads();
-        const int k = __builtin_amdgcn_readfirstlane(s_item);
-        if (k >= nitems) break;
-        const QItem& qi = items[k];
-        const QFold& qf = folds[qi.fold];
-        const int NT = qf.f.NT, A = qi.A, d = qi.d;
-        if (qi.kind == kQDiag) {
-            TileWork w{};
-            w.f = qf.f;
-            w.A = A;
-            diag_body<Q>(w, u.dg, tid, kTileThreads);
-            signal_add(qf.done + tile_index(NT, A, 0));
-        } else if (qi.kind == kQFinish) {
-            TileWork w{};
-            w.f = qf.f;
-            w.acc = qf.acc + (size_t)(2 * A + (d & 1)) * kTileCells;
-            w.A = A;
-            w.d = d;
-            w.nslot = qi.aux > 0 ? 1 : 0;
-            const int32_t* dn = qf.done;
-            auto pre = [&] { wait_ge(dn + tile_index(NT, A, 0), 1, dn + tile_index(NT, A + d, 0), 1, nullptr, 0, err); };
-            auto deps = [&] {
-                if (d >= 2)
-                    wait_ge(dn + tile_index(NT, A, d - 1), 1, dn + tile_index(NT, A + 1, d - 1), 1,
-                            qi.aux > 0 ? qf.bcnt + tile_index(NT, A, d) : nullptr, qi.aux, err);
-            };
-            tile_body<Q>(w, Rl, u.t, pre, deps);
-            signal_add(qf.done + tile_index(NT, A, d));
-        } else {
-            BetweenWork w{};
-            w.f = qf.f;
-            w.acc = qf.acc + (size_t)(2 * A + (d & 1)) * kTileCells;
-            w.A = A;
-            w.d = d;
-            w.c0 = qi.c0;
-            w.c1 = qi.c1;
-            w.atomic = qi.aux;
-            // tile (A, A+d-2) covers the row tiles (A, C <= A+d-2) and is the
-            // accumulator's previous reader; tile (c0, A+d) covers the column
-            // tiles (C >= c0, A+d)
-            wait_ge(qf.done + tile_index(NT, A, d - 2), 1, qf.done + tile_index(NT, qi.c0, A + d - qi.c0), 1,
-                    nullptr, 0, err);
-            // the strips were written during this launch: keep their loads
-            // (scalar loads among them) below the wait
-            uint64_t rs = (uint64_t)qf.f.RS, cs = (uint64_t)qf.f.CS;
-            asm volatile("" : "+s"(rs), "+s"(cs));
-            const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-            between_body<Q, kQueueRowsPerWave>(w, Rl, (const uint32_t*)rs, (const uint32_t*)cs, wave, tid & 63);
-            signal_add(qf.bcnt + tile_index(NT, A, d));
-        }
-    }
-}
-
-__global__ void k_scores(const FoldDesc* __restrict__ folds, int nfolds, int32_t* __restrict__ scores,
-                         const int32_t* __restrict__ err)
+__global__ void k_scores(const FoldDesc* __restrict__ folds, int nfolds, int32_t* __restrict__ scores)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < nfolds) scores[e] = (err && *err) ? -1 : folds[e].F[folds[e].n];  // F(0, n) = D(1, n)
-}
-
-__global__ void k_zero(int32_t* __restrict__ p, long long count)
-{
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < count) p[e] = 0;
+    if (e < nfolds) scores[e] = folds[e].F[folds[e].n];  // F(0, n) = D(1, n)
 }
 
 // S[i*n + j] = D(i+1, j+1) = F(i, j+1) for i <= j, 0 below the diagonal.
@@ -883,38 +791,12 @@ hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uin
     return dispatch(q, 2, items, nitems, R, s, e0, e1);
 }
 
-hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, const int32_t* err, hipStream_t s)
+hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s)
 {
     if (nfolds <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scores, dim3((nfolds + 255) / 256), dim3(256), 0, s, folds, nfolds, scores, err);
+    hipLaunchKernelGGL(k_scores, dim3((nfolds + 255) / 256), dim3(256), 0, s, folds, nfolds, scores);
     return hipGetLastError();
 }
-
-hipError_t launch_zero(int32_t* p, long long count, hipStream_t s)
-{
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count);
-    return hipGetLastError();
-}
-
-namespace {
-template <int Q>
-hipError_t queue_q(const QItem* items, int nitems, const QFold* folds, const uint8_t* R, int* head, int* err,
-                   int blocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
-{
-    return launch_k(k_queue<Q>, dim3(blocks), dim3(kTileThreads), s, e0, e1, items, nitems, folds, R, head, err);
-}
-template <int Q>
-int occupancy_q()
-{
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_queue<Q>, kTileThreads, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    return nb;
-}
-}  // namespace
 
 namespace {
 template <int Q>
@@ -939,39 +821,6 @@ hipError_t launch_stage(int q, const TileWork* titems, int ntile, const BetweenW
     case 7: return stage_q<7>(titems, ntile, bitems, nbtw, R, s, e0, e1);
     case 8: return stage_q<8>(titems, ntile, bitems, nbtw, R, s, e0, e1);
     default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_queue(int q, const QItem* items, int nitems, const QFold* folds, const uint8_t* R, int* head,
-                        int* err, int blocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
-{
-    if (nitems <= 0) return hipSuccess;
-    if (blocks <= 0) return hipErrorInvalidValue;
-    switch (q) {
-    case 1: return queue_q<1>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
-    case 2: return queue_q<2>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
-    case 3: return queue_q<3>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
-    case 4: return queue_q<4>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
-    case 5: return queue_q<5>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
-    case 6: return queue_q<6>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
-    case 7: return queue_q<7>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
-    case 8: return queue_q<8>(items, nitems, folds, R, head, err, blocks, s, e0, e1);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-int queue_blocks_per_cu(int q)
-{
-    switch (q) {
-    case 1: return occupancy_q<1>();
-    case 2: return occupancy_q<2>();
-    case 3: return occupancy_q<3>();
-    case 4: return occupancy_q<4>();
-    case 5: return occupancy_q<5>();
-    case 6: return occupancy_q<6>();
-    case 7: return occupancy_q<7>();
-    case 8: return occupancy_q<8>();
-    default: return 0;
     }
 }
 

@@ -159,15 +159,13 @@ Geom make_geom(int n, int q)
     return g;
 }
 
-// Between chunks per wavefront step (NF_BETWEEN_TARGET overrides).  Launches
-// per step want enough workgroups to fill the device; the persistent queue
-// pays a wait and a release per item, so it wants few, large chunks.
-int between_target(int mode)
+// Between chunks per wavefront step (NF_BETWEEN_TARGET overrides): enough
+// workgroups to fill the device.
+int between_target(int /*mode*/)
 {
     const char* e = getenv("NF_BETWEEN_TARGET");
     const int env = e ? atoi(e) : 0;
-    if (env > 0) return env;
-    return mode == kModeQueue ? 128 : 1024;
+    return env > 0 ? env : 1024;
 }
 
 // Append the between-group items of diagonal dd for the listed folds.  The
@@ -266,61 +264,8 @@ void build_schedule(const std::vector<int>& NTs, int target, Schedule& sc)
         if (sc.tile[k].nslot > 0) sc.tile[k].slot0 += ((tile_stage[k] - 1) & 1) * max_slots;
 }
 
-// The persistent fill's work queue: the schedule's own order (diagonal tiles,
-// then per step the finishes of diagonal s followed by the between chunks of
-// diagonal s+1).  Every wait of an item must be met by items placed before
-// it; that is checked here, so a plan whose queue could stall is refused.
-int build_queue(const Schedule& sc, const std::vector<int>& NTs, std::vector<QItem>& out)
-{
-    out.clear();
-    std::vector<std::vector<char>> done(NTs.size());
-    std::vector<std::vector<int>> chunks(NTs.size()), seen(NTs.size());
-    for (size_t f = 0; f < NTs.size(); ++f) {
-        const size_t tc = (size_t)tile_count(NTs[f]);
-        done[f].assign(tc, 0);
-        chunks[f].assign(tc, 0);
-        seen[f].assign(tc, 0);
-    }
-    for (const BetweenItem& b : sc.btw) chunks[b.fold][tile_index(NTs[b.fold], b.A, b.d)] += 1;
-    auto is_done = [&](int f, int A, int d) { return d >= 0 && A >= 0 && A + d < NTs[f] && done[f][tile_index(NTs[f], A, d)]; };
-    auto add_tile = [&](const TileItem& t, int kind) -> int {
-        const int f = t.fold, A = t.A, d = t.d, NT = NTs[f];
-        QItem q{kind, f, A, d, 0, 0, 0, 0};
-        if (kind == kQFinish) {
-            q.aux = chunks[f][tile_index(NT, A, d)];
-            bool ok = is_done(f, A, 0) && is_done(f, A + d, 0);
-            if (d >= 2) ok = ok && is_done(f, A, d - 1) && is_done(f, A + 1, d - 1) &&
-                             seen[f][tile_index(NT, A, d)] == q.aux;
-            if (!ok) return fail(NF_E_DEVICE, "work queue order broken at finish (%d, %d) of fold %d", A, A + d, f);
-        }
-        out.push_back(q);
-        done[f][tile_index(NT, A, d)] = 1;
-        return NF_OK;
-    };
-    for (int sg = 0; sg < sc.stages; ++sg) {
-        int rc;
-        if (sg == 0) {
-            for (const TileItem& t : sc.diag)
-                if ((rc = add_tile(t, kQDiag))) return rc;
-        } else {
-            for (int k = 0; k < sc.tile_cnt[sg]; ++k)
-                if ((rc = add_tile(sc.tile[sc.tile_off[sg] + k], kQFinish))) return rc;
-        }
-        for (int k = 0; k < sc.btw_cnt[sg]; ++k) {
-            const BetweenItem& b = sc.btw[sc.btw_off[sg] + k];
-            const int f = b.fold, NT = NTs[f];
-            if (!(b.d >= 4 && b.c0 >= b.A + 2 && b.c1 <= b.A + b.d - 1 && b.c0 < b.c1 && is_done(f, b.A, b.d - 2) &&
-                  is_done(f, b.c0, b.A + b.d - b.c0)))
-                return fail(NF_E_DEVICE, "work queue order broken at between (%d, %d) of fold %d", b.A, b.A + b.d, f);
-            out.push_back(QItem{kQBetween, f, b.A, b.d, b.c0, b.c1, b.pad0, 0});
-            seen[f][tile_index(NT, b.A, b.d)] += 1;
-        }
-    }
-    return NF_OK;
-}
-
-// Execution of a new plan.  NF_MODE = "staged", "fused" or "queue" forces
-// one (see PlanMode); otherwise fused steps when the tiles of one step are
+// Execution of a new plan.  NF_MODE = "staged" or "fused" forces one (see
+// PlanMode); otherwise fused steps when the tiles of one step are
 // few (the step is latency-bound: one launch and no cross-stream wait per
 // step is cheapest), staged steps when the between chunks of a step fill the
 // device (the two-stream form runs them at full occupancy).  Measured on
@@ -331,7 +276,6 @@ constexpr long long kFusedMaxTilesPerSide = 208;
 int plan_mode_for(const std::vector<int>& NTs)
 {
     if (const char* e = getenv("NF_MODE")) {  // read per plan: cached plans keep their mode
-        if (strcmp(e, "queue") == 0) return kModeQueue;
         if (strcmp(e, "fused") == 0) return kModeFused;
         if (strcmp(e, "staged") == 0) return kModeStaged;
     }
@@ -433,77 +377,12 @@ int plan_allocate(Plan& p)
         HIPCHK(hipMemcpyAsync(p.d_tile.p, wt.data(), wt.size() * sizeof(TileWork), hipMemcpyHostToDevice, s));
     if (!wb.empty())
         HIPCHK(hipMemcpyAsync(p.d_btw.p, wb.data(), wb.size() * sizeof(BetweenWork), hipMemcpyHostToDevice, s));
-    if (p.mode == kModeQueue) {
-        std::vector<int> NTs;
-        for (auto& g : p.geom) NTs.push_back(g.NT);
-        std::vector<QItem> qi;
-        if ((rc = build_queue(sc, NTs, qi))) return rc;
-        p.nqitems = (int)qi.size();
-        // counters: [head, err, 14 pad] then per fold done[tiles], bcnt[tiles]
-        size_t acc_cells = 0;
-        long long ints = 16;
-        for (int nt : NTs) {
-            acc_cells += (size_t)2 * nt * kTileCells;
-            ints += 2 * tile_count(nt);
-        }
-        p.qstate_ints = ints;
-        if ((rc = p.d_qitems.alloc(std::max<size_t>(1, qi.size()) * sizeof(QItem)))) return rc;
-        if ((rc = p.d_qfolds.alloc(std::max<size_t>(1, fd.size()) * sizeof(QFold)))) return rc;
-        if ((rc = p.d_qacc.alloc(std::max<size_t>(1, acc_cells) * sizeof(int32_t)))) return rc;
-        if ((rc = p.d_qstate.alloc((size_t)ints * sizeof(int32_t)))) return rc;
-        std::vector<QFold> qf(fd.size());
-        int32_t* acc = (int32_t*)p.d_qacc.p;
-        int32_t* st = (int32_t*)p.d_qstate.p + 16;
-        for (size_t f = 0; f < fd.size(); ++f) {
-            const long long tc = tile_count(NTs[f]);
-            qf[f].f = fd[f];
-            qf[f].acc = acc;
-            qf[f].done = st;
-            qf[f].bcnt = st + tc;
-            qf[f].pad = nullptr;
-            acc += (size_t)2 * NTs[f] * kTileCells;
-            st += 2 * tc;
-        }
-        // accumulators start at zero; every run leaves them zero again
-        HIPCHK(hipMemsetAsync(p.d_qacc.p, 0, p.d_qacc.bytes, s));
-        if (!qi.empty())
-            HIPCHK(hipMemcpyAsync(p.d_qitems.p, qi.data(), qi.size() * sizeof(QItem), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(p.d_qfolds.p, qf.data(), qf.size() * sizeof(QFold), hipMemcpyHostToDevice, s));
-        Context& c = ctx();
-        if (!c.queue_blocks[p.q]) c.queue_blocks[p.q] = queue_blocks_per_cu(p.q);
-        if (c.queue_blocks[p.q] <= 0) return fail(NF_E_DEVICE, "persistent fill kernel cannot be resident (q = %d)", p.q);
-    }
     HIPCHK(hipStreamSynchronize(s));
     p.device_bytes = p.arena.bytes + p.d_folds.bytes + p.d_diag.bytes + p.d_tile.bytes + p.d_btw.bytes +
-                     p.d_part.bytes + p.d_scores.bytes + p.d_qitems.bytes + p.d_qfolds.bytes + p.d_qacc.bytes +
-                     p.d_qstate.bytes;
+                     p.d_part.bytes + p.d_scores.bytes;
     return NF_OK;
 }
 
-// The persistent fill: zero the counters (a kernel, so the run can be
-// captured), drain the queue with every resident workgroup, read the scores.
-static int plan_enqueue_queue(Plan& p, hipStream_t s)
-{
-    const uint8_t* R = nullptr;
-    int rc = get_R(p.q, &R);
-    if (rc) return rc;
-    Context& c = ctx();
-    int32_t* st = (int32_t*)p.d_qstate.p;
-    const int blocks = std::max(1, std::min(p.nqitems, c.queue_blocks[p.q] * c.num_cu));
-    HIPCHK(launch_zero(st, p.qstate_ints, s));
-    HIPCHK(launch_queue(p.q, (const QItem*)p.d_qitems.p, p.nqitems, (const QFold*)p.d_qfolds.p, R, st, st + 1, blocks,
-                        s));
-    HIPCHK(launch_scores((const FoldDesc*)p.d_folds.p, (int)p.geom.size(), (int32_t*)p.d_scores.p, st + 1, s));
-    return NF_OK;
-}
-
-// The fill of every fold in the plan: diagonal tiles, then per stage the
-// tile finishes of diagonal s (on stream s) and, on a second stream, the
-// between-group work of diagonal s+1, which only needs diagonals <= s-1 and
-// so overlaps the finishes.  Events order the two streams:
-//     finish(s)    after between(s-1)  (its between maxima)
-//     between(s)   after finish(s-1)   (its inputs; also frees its accumulators)
-// Under graph capture the events become graph edges.
 // Fused steps: one launch per step on one stream.  Kernel order alone gives
 //     finish(s)  after between(s)  (in launch s-1)
 //     between(s+1) after finish(s-1) (launch s-1)
@@ -523,13 +402,12 @@ static int plan_enqueue_fused(Plan& p, hipStream_t s)
                                 (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R, s));
         }
     }
-    HIPCHK(launch_scores((const FoldDesc*)p.d_folds.p, (int)p.geom.size(), (int32_t*)p.d_scores.p, nullptr, s));
+    HIPCHK(launch_scores((const FoldDesc*)p.d_folds.p, (int)p.geom.size(), (int32_t*)p.d_scores.p, s));
     return NF_OK;
 }
 
 int plan_enqueue_direct(Plan& p, hipStream_t s)
 {
-    if (p.mode == kModeQueue) return plan_enqueue_queue(p, s);
     if (p.mode == kModeFused) return plan_enqueue_fused(p, s);
     const uint8_t* R = nullptr;
     int rc = get_R(p.q, &R);
@@ -557,7 +435,7 @@ int plan_enqueue_direct(Plan& p, hipStream_t s)
     // join the side stream back into s
     HIPCHK(hipEventRecord(ev_btw, s2));
     HIPCHK(hipStreamWaitEvent(s, ev_btw, 0));
-    HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, nullptr, s));
+    HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, s));
     return NF_OK;
 }
 
@@ -628,25 +506,7 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
         return e0 && e1;
     };
     hipEvent_t a = nullptr, b = nullptr;
-    if (p.mode == kModeQueue) {
-        double lk = 0, sp = diag_sp, cells = diag_cells;
-        for (int sg = 0; sg < sc.stages; ++sg) {
-            lk += tile_lk[sg] + btw_lk[sg];
-            sp += tile_sp[sg];
-            cells += tile_cells[sg];
-        }
-        Context& c = ctx();
-        int32_t* st = (int32_t*)p.d_qstate.p;
-        const int blocks = std::max(1, std::min(p.nqitems, c.queue_blocks[p.q] * c.num_cu));
-        for (int r = 0; r < reps; ++r) {
-            HIPCHK(launch_zero(st, p.qstate_ints, s));
-            if (!pair(a, b)) return fail(NF_E_DEVICE, "event creation failed");
-            HIPCHK(launch_queue(p.q, (const QItem*)p.d_qitems.p, p.nqitems, (const QFold*)p.d_qfolds.p, R, st, st + 1,
-                                blocks, s, a, b));
-            recs.push_back({3, a, b, lk, sp, cells});
-            HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, st + 1, s));
-        }
-    } else {
+    {
         const bool fused = p.mode == kModeFused;
         for (int r = 0; r < reps; ++r) {
             if (!pair(a, b)) return fail(NF_E_DEVICE, "event creation failed");
@@ -659,7 +519,7 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
                     if (sc.tile_cnt[sg] + sc.btw_cnt[sg] == 0) continue;
                     if (!pair(a, b)) return fail(NF_E_DEVICE, "event creation failed");
                     HIPCHK(launch_stage(p.q, tw, sc.tile_cnt[sg], bw, sc.btw_cnt[sg], R, s, a, b));
-                    recs.push_back({4, a, b, tile_lk[sg] + btw_lk[sg], tile_sp[sg], tile_cells[sg]});
+                    recs.push_back({3, a, b, tile_lk[sg] + btw_lk[sg], tile_sp[sg], tile_cells[sg]});
                     continue;
                 }
                 if (sg >= 1 && sc.tile_cnt[sg] > 0) {
@@ -673,7 +533,7 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
                     recs.push_back({2, a, b, btw_lk[sg], 0.0, 0.0});
                 }
             }
-            HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, nullptr, s));
+            HIPCHK(launch_scores(folds, (int)p.geom.size(), (int32_t*)p.d_scores.p, s));
         }
     }
     HIPCHK(hipStreamSynchronize(s));

@@ -61,9 +61,8 @@ struct Schedule {
 //   staged: per wavefront step, the tile finishes of diagonal s on one stream
 //           and the between chunks of diagonal s+1 on a second one;
 //   fused:  per step one launch holding both (one stream, no cross-stream
-//           waits);
-//   queue:  one persistent launch draining a dependency-ordered work queue.
-enum PlanMode { kModeStaged = 0, kModeQueue = 1, kModeFused = 2 };
+//           waits).
+enum PlanMode { kModeStaged = 0, kModeFused = 1 };
 
 struct Plan {
     int q = 8;
@@ -73,11 +72,6 @@ struct Plan {
     Schedule sc;
     DevBuf arena, d_folds, d_diag, d_tile, d_btw, d_part, d_scores;
     DevBuf d_S;  // expand target for host copies of tables
-    // persistent-queue mode: items, per-fold descriptors, accumulators and
-    // the counters zeroed before every run ([head, err, pad..., done/bcnt])
-    DevBuf d_qitems, d_qfolds, d_qacc, d_qstate;
-    int nqitems = 0;
-    long long qstate_ints = 0;
     size_t device_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -100,7 +94,6 @@ struct Context {
     DevBuf R[NF_Q_MAX + 1];
     std::vector<std::pair<long long, std::unique_ptr<Plan>>> plans;  // LRU, most recent last
     int tuned_q[kTuneBuckets] = {0};
-    int queue_blocks[NF_Q_MAX + 1] = {0};  // resident persistent workgroups per CU, by q
     bool tune_loaded = false;
 };
 
@@ -122,7 +115,6 @@ TileWork to_work(const TileItem& it, const std::vector<FoldDesc>& fd, int32_t* a
 BetweenWork to_work(const BetweenItem& it, const std::vector<FoldDesc>& fd, int32_t* acc_base);
 int plan_enqueue(Plan& p, hipStream_t s);
 int plan_enqueue_direct(Plan& p, hipStream_t s);
-int build_queue(const Schedule& sc, const std::vector<int>& NTs, std::vector<QItem>& out);
 int plan_mode_for(const std::vector<int>& NTs);
 int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out);
 int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out);

@@ -500,7 +500,7 @@ void engine_main()
         ok = ok && hipEventRecord(D.ev_btw, D.s2) == hipSuccess;
         // finished folds: score (and table) to pinned memory
         if (ok && !rec.finishing.empty()) {
-            ok = launch_scores(d_fin, (int)wfin.size(), (int32_t*)D.d_scores.p, nullptr, D.s1) == hipSuccess;
+            ok = launch_scores(d_fin, (int)wfin.size(), (int32_t*)D.d_scores.p, D.s1) == hipSuccess;
             for (size_t k = 0; ok && k < rec.finishing.size(); ++k) {
                 Active* a = rec.finishing[k];
                 ok = hipMemcpyAsync(D.h_scores + a->slot, (int32_t*)D.d_scores.p + k, sizeof(int32_t),

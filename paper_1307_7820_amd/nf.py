@@ -59,13 +59,13 @@ class ServeStats(ctypes.Structure):
 
 
 class KernelProfile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 5), ("ms", ctypes.c_double * 5),
-                ("lookups", ctypes.c_double * 5), ("splits", ctypes.c_double * 5), ("cells", ctypes.c_double * 5),
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("ms", ctypes.c_double * 4),
+                ("lookups", ctypes.c_double * 4), ("splits", ctypes.c_double * 4), ("cells", ctypes.c_double * 4),
                 ("q", ctypes.c_int), ("tile", ctypes.c_int), ("tiles_per_side", ctypes.c_int),
                 ("stages", ctypes.c_int)]
 
 
-KERNEL_NAMES = ("k_diag", "k_tile", "k_between", "k_queue", "k_stage")
+KERNEL_NAMES = ("k_diag", "k_tile", "k_between", "k_stage")
 
 _lib = None
 
