@@ -37,8 +37,11 @@
 
 namespace nf {
 
-constexpr int kThreads = 256;     // 4 wavefronts of 64 per workgroup
-constexpr int kRowsPerWave = 16;  // rows of a 64x64 tile held by one wavefront
+constexpr int kThreads = 256;  // main-diagonal tiles: 4 wavefronts of 64 per workgroup
+// between-group chunks: 4 wavefronts of 16 rows each (8 of 8 rows measured
+// slightly slower: twice the column-word loads for the same lookups)
+constexpr int kBetweenThreads = 256;
+constexpr int kRowsPerWave = 64 / (kBetweenThreads / 64);
 constexpr int kTileCells = 64 * 64;
 
 __host__ __device__ constexpr int groups_per_tile(int q) { return 64 / q; }

@@ -128,12 +128,25 @@ __device__ __forceinline__ void diag_body(const TileWork& it, DiagLds& s, int ti
     }
     __syncthreads();
 
+    // diagonal t: cell (i, i+t) takes max over its split points m; eight
+    // lanes share a cell (lane k of the group takes m = i+1+k, i+9+k, ...)
+    // and combine their maxima inside the group with DPP (mirror within 8
+    // lanes, then two quad permutations).  Every value is >= 0, so 0 is the
+    // identity of max here.
+    const int grp = tid >> 3, sub = tid & 7, ngrp = nthr >> 3;
     for (int t = 2; t < T; ++t) {
-        for (int i = tid; i < T - t; i += nthr) {
+        for (int i0 = 0; i0 < T - t; i0 += ngrp) {
+            const int i = i0 + grp;
             const int j = i + t;
-            int v = (s.ca[i] + s.cb[j] == 3) + X[(i + 1) * XS + (j - 1)];
-            for (int m = i + 1; m < j; ++m) v = max(v, X[i * XS + m] + X[m * XS + j]);
-            X[i * XS + j] = v;
+            const bool live = i < T - t;
+            int v = 0;
+            if (live) {
+                for (int m = i + 1 + sub; m < j; m += 8) v = max(v, X[i * XS + m] + X[m * XS + j]);
+            }
+            v = max(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));  // row_half_mirror
+            v = max(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));   // quad_perm [1,0,3,2]
+            v = max(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));   // quad_perm [2,3,0,1]
+            if (live && sub == 0) X[i * XS + j] = max(v, (s.ca[i] + s.cb[j] == 3) + X[(i + 1) * XS + (j - 1)]);
         }
         __syncthreads();
     }
@@ -176,14 +189,14 @@ __device__ __forceinline__ void between_body(const BetweenWork& it, const uint8_
 }
 
 template <int Q>
-__global__ __launch_bounds__(kThreads) void k_between(const BetweenWork* __restrict__ items,
+__global__ __launch_bounds__(kBetweenThreads) void k_between(const BetweenWork* __restrict__ items,
                                                       const uint8_t* __restrict__ Rg)
 {
     constexpr int RSZ = 1 << (2 * (Q - 1));
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
 
     const BetweenWork& it = items[blockIdx.x];
-    load_R<RSZ>(Rl, Rg, kThreads);
+    load_R<RSZ>(Rl, Rg, kBetweenThreads);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     between_body<Q, kRowsPerWave>(it, Rl, it.f.RS, it.f.CS, wave, threadIdx.x & 63);
@@ -735,10 +748,10 @@ hipError_t launch_q(int which, const void* items, int nitems, const uint8_t* R, 
                     hipEvent_t e1)
 {
     if (nitems <= 0) return hipSuccess;
-    dim3 grid(nitems), block(kThreads);
-    if (which == 0) return launch_k(k_diag<Q>, grid, block, s, e0, e1, (const TileWork*)items);
+    dim3 grid(nitems);
+    if (which == 0) return launch_k(k_diag<Q>, grid, dim3(kThreads), s, e0, e1, (const TileWork*)items);
     if (which == 1) return launch_k(k_tile<Q>, grid, dim3(kTileThreads), s, e0, e1, (const TileWork*)items, R);
-    return launch_k(k_between<Q>, grid, block, s, e0, e1, (const BetweenWork*)items, R);
+    return launch_k(k_between<Q>, grid, dim3(kBetweenThreads), s, e0, e1, (const BetweenWork*)items, R);
 }
 
 hipError_t dispatch(int q, int which, const void* items, int nitems, const uint8_t* R, hipStream_t s, hipEvent_t e0,
