@@ -38,10 +38,14 @@
 namespace nf {
 
 constexpr int kThreads = 256;  // main-diagonal tiles: 4 wavefronts of 64 per workgroup
-// between-group chunks: 4 wavefronts of 16 rows each (8 of 8 rows measured
-// slightly slower: twice the column-word loads for the same lookups)
-constexpr int kBetweenThreads = 256;
-constexpr int kRowsPerWave = 64 / (kBetweenThreads / 64);
+// between-group chunks: 8 wavefronts.  A wavefront owns 16 rows (8 rows
+// measured slower: twice the column-word loads for the same lookups); two
+// wavefronts share each block of rows and take alternate groups of split
+// points.
+constexpr int kBetweenThreads = 512;
+constexpr int kRowsPerWave = 16;
+constexpr int kBetweenSplit = kBetweenThreads / 64 / (64 / kRowsPerWave);
+static_assert(kBetweenSplit == 1 || kBetweenSplit == 2, "one or two wavefronts per row block");
 constexpr int kTileCells = 64 * 64;
 
 __host__ __device__ constexpr int groups_per_tile(int q) { return 64 / q; }

@@ -56,11 +56,13 @@ __device__ __forceinline__ void load_R(uint8_t* Rl, const uint8_t* __restrict__ 
 // For group k of tile C the row word comes from tile (A, C) and the column
 // word from tile (C, B); Eq. 3 turns the q split points of the group into
 //     F(a, Cq') + F(Cq', b) + R[h][c].
-template <int Q, int RPW>
+// With NS > 1 the caller's share is every NS-th group of the flattened
+// (C, k) sequence, starting at group h.
+template <int Q, int RPW, int NS>
 __device__ __forceinline__ void between_accumulate(int (&acc)[RPW], const uint8_t* Rl,
                                                    const uint32_t* __restrict__ RS,
                                                    const uint32_t* __restrict__ CS, int NT, int A,
-                                                   int B, int c0, int c1, int r0, int j)
+                                                   int B, int c0, int c1, int r0, int j, int h)
 {
     constexpr int G = groups_per_tile(Q);
     constexpr int SW = state_words(Q);
@@ -69,8 +71,9 @@ __device__ __forceinline__ void between_accumulate(int (&acc)[RPW], const uint8_
         const NF_CONST uint32_t* rb = as_const(RS + tile_index(NT, A, C - A) * RW + r0);  // bases
         const NF_CONST uint32_t* rh = rb + G * 64;                                         // bits
         const NF_GLOBAL uint32_t* cs = as_global(CS + tile_index(NT, C, B - C) * SW + j);
+        const int k0 = (G % NS == 0) ? h : ((h - (C - c0) * G) % NS + NS) % NS;
 #pragma unroll 2
-        for (int k = 0; k < G; ++k) {
+        for (int k = k0; k < G; k += NS) {
             const uint32_t cw = cs[k * 64];
             const uint32_t clo = cw & 0xffffu;
             const int chi = (int)(cw >> 16);
@@ -166,17 +169,34 @@ __global__ __launch_bounds__(kThreads) void k_diag(const TileWork* __restrict__ 
     diag_body<Q>(items[blockIdx.x], s, threadIdx.x, kThreads);
 }
 
-// One between item: rows r0 = wave * RPW .. +RPW-1 and column j (the lane)
-// of the tile's 64x64 maxima, written to its accumulator.
-template <int Q, int RPW>
+// One between item: rows r0 .. r0+RPW-1 and column j (the lane) of the tile's
+// 64x64 maxima, written to its accumulator.  Wavefront w takes the row block
+// w % (64/RPW); with NS = 2 the two wavefronts of a row block split the
+// groups and merge their maxima through red (64x64 ints of LDS).  Every
+// thread of the workgroup must call this.
+template <int Q, int RPW, int NS>
 __device__ __forceinline__ void between_body(const BetweenWork& it, const uint8_t* Rl,
-                                             const uint32_t* RS, const uint32_t* CS, int wave, int j)
+                                             const uint32_t* RS, const uint32_t* CS, int wave, int j,
+                                             int32_t* red)
 {
-    const int r0 = wave * RPW;
+    constexpr int NB = 64 / RPW;
+    static_assert(NS == 1 || NS == 2, "one or two wavefronts per row block");
+    const int h = wave / NB;
+    const int r0 = (wave - h * NB) * RPW;
     int acc[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) acc[r] = 0;
-    between_accumulate<Q, RPW>(acc, Rl, RS, CS, it.f.NT, it.A, it.A + it.d, it.c0, it.c1, r0, j);
+    between_accumulate<Q, RPW, NS>(acc, Rl, RS, CS, it.f.NT, it.A, it.A + it.d, it.c0, it.c1, r0, j, h);
+    if constexpr (NS == 2) {
+        if (h == 1) {
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) red[(r0 + r) * 64 + j] = acc[r];
+        }
+        __syncthreads();
+        if (h == 1) return;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) acc[r] = max(acc[r], red[(r0 + r) * 64 + j]);
+    }
 
     int32_t* out = it.acc + r0 * 64 + j;
     if (it.atomic) {  // several items share the tile's accumulator
@@ -194,12 +214,13 @@ __global__ __launch_bounds__(kBetweenThreads) void k_between(const BetweenWork* 
 {
     constexpr int RSZ = 1 << (2 * (Q - 1));
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
+    __shared__ int32_t red[kBetweenSplit == 2 ? 64 * 64 : 1];
 
     const BetweenWork& it = items[blockIdx.x];
     load_R<RSZ>(Rl, Rg, kBetweenThreads);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    between_body<Q, kRowsPerWave>(it, Rl, it.f.RS, it.f.CS, wave, threadIdx.x & 63);
+    between_body<Q, kRowsPerWave, kBetweenSplit>(it, Rl, it.f.RS, it.f.CS, wave, threadIdx.x & 63, red);
 }
 
 // Finish of an off-diagonal tile (A, B), B > A, by 8 wavefronts (512 threads).
@@ -696,7 +717,6 @@ __global__ __launch_bounds__(kTileThreads) void k_stage(const TileWork* __restri
                                                         const uint8_t* __restrict__ Rg)
 {
     constexpr int RSZ = 1 << (2 * (Q - 1));
-    constexpr int kRows = 64 / (kTileThreads / 64);
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
     __shared__ __align__(16) TileLds<Q> s;
     const int b = blockIdx.x;
@@ -707,7 +727,7 @@ __global__ __launch_bounds__(kTileThreads) void k_stage(const TileWork* __restri
         __syncthreads();
         const BetweenWork& it = bitems[b - ntile];
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        between_body<Q, kRows>(it, Rl, it.f.RS, it.f.CS, wave, threadIdx.x & 63);
+        between_body<Q, 16, kTileThreads / 64 / 4>(it, Rl, it.f.RS, it.f.CS, wave, threadIdx.x & 63, s.Xs);
     }
 }
 
