@@ -89,10 +89,10 @@ int nf_copy_R(int q, uint8_t* out, size_t cap);
  * (layout above) is written to it.  Synchronous.
  *
  * Execution (Sections 4-5: the wavefront over tile diagonals), chosen per
- * workspace: when a step holds few tiles (one fold up to n of about 13000)
- * each step is one launch holding the finishes of diagonal s and the
- * between-group chunks of diagonal s+1; otherwise the two kinds run as
- * separate launches on two streams.  NF_MODE=staged|fused forces one. */
+ * workspace: for one fold, and for batches whose steps hold few tiles, each
+ * step is one launch holding the finishes of diagonal s and the
+ * between-group chunks of diagonal s+1; for larger batches the two kinds run
+ * as separate launches on two streams.  NF_MODE=staged|fused forces one. */
 int nf_fold(const char* seq, int n, int q, int16_t* S_out);
 
 /* ---- Single fold (device buffers, asynchronous on a HIP stream) ----

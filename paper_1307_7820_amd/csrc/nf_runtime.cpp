@@ -265,12 +265,12 @@ void build_schedule(const std::vector<int>& NTs, int target, Schedule& sc)
 }
 
 // Execution of a new plan.  NF_MODE = "staged" or "fused" forces one (see
-// PlanMode); otherwise fused steps when the tiles of one step are
-// few (the step is latency-bound: one launch and no cross-stream wait per
-// step is cheapest), staged steps when the between chunks of a step fill the
-// device (the two-stream form runs them at full occupancy).  Measured on
-// MI355X: fused is faster for one fold up to n = 12000, staged at n = 16000
-// and for a batch of 4096 folds.
+// PlanMode); otherwise fused steps for one fold and for batches whose steps
+// hold few tiles (one launch and no cross-stream wait per step is cheapest),
+// staged steps for large batches (many folds' tiles and chunks per step fill
+// the device on two streams).  Measured on MI355X: fused is faster for one
+// fold at n = 6000, 12000 and 16000 (2.19 / 6.94 / 13.6 ms against 3.07 /
+// 8.19 / 14.6 ms), staged for a batch of 4096 folds (21.2 against 22.6 ms).
 constexpr long long kFusedMaxTilesPerSide = 208;
 
 int plan_mode_for(const std::vector<int>& NTs)
@@ -279,6 +279,7 @@ int plan_mode_for(const std::vector<int>& NTs)
         if (strcmp(e, "fused") == 0) return kModeFused;
         if (strcmp(e, "staged") == 0) return kModeStaged;
     }
+    if (NTs.size() == 1) return kModeFused;
     long long sum = 0;
     for (int nt : NTs) sum += nt;
     return sum <= kFusedMaxTilesPerSide ? (int)kModeFused : (int)kModeStaged;
