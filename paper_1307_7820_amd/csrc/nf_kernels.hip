@@ -292,7 +292,9 @@ struct TileLds {
     uint2 EB[kStageEdges ? 2 * G * 64 : 1];      // EB[(e*G + k)*64 + row] = {base, bits}, end tile e
     uint32_t EC[kStageEdges ? 2 * G * 64 : 1];  // EC[(e*G + k)*64 + col] = column word, end tile e
     int32_t Qs[2][64];    // Q of the row being closed (double-buffered)
-    int32_t hrow[64], hcol[64];
+    int32_t hrow[64];
+    alignas(16) int32_t hcT[64];  // hcT[8g + b] = halo partner of column 0 in row 8b + g
+    alignas(16) uint8_t caT[64];  // caT[8g + b] = S_{a+1} of row 8b + g
     uint8_t ca[64], cb[64];
     unsigned long long GM[8];  // GM[g] bit i: pairing of (row i, column 8g)
 };
@@ -324,7 +326,8 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     uint32_t* EC = s.EC;
     int32_t (*Qs)[64] = s.Qs;
     int32_t* hrow = s.hrow;
-    int32_t* hcol = s.hcol;
+    int32_t* hcT = s.hcT;
+    uint8_t* caT = s.caT;
     uint8_t* ca = s.ca;
     uint8_t* cb = s.cb;
     unsigned long long* GM = s.GM;
@@ -434,6 +437,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     if (tid < 64) {
         ca[tid] = cda;
         cb[tid] = cdb;
+        caT[(tid & 7) * 8 + (tid >> 3)] = cda;  // transposed: one 8-byte read per lane
     }
     if constexpr (kStageEdges) {
 #pragma unroll
@@ -446,10 +450,8 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             }
         }
     }
-    if (tid < T) {
-        hrow[tid] = hrv;
-        hcol[tid] = hcv;
-    }
+    if (tid < T) hrow[tid] = hrv;
+    if (tid < 64) hcT[(tid & 7) * 8 + (tid >> 3)] = hcv;  // hcv = 0 for rows >= T
     // this thread holds L(8u + wave, lane), u = 0..7: eight consecutive words
     *reinterpret_cast<int4*>(&Lp[lane * LS + 8 * wave]) = make_int4(lv[0], lv[1], lv[2], lv[3]);
     *reinterpret_cast<int4*>(&Lp[lane * LS + 8 * wave + 4]) = make_int4(lv[4], lv[5], lv[6], lv[7]);
@@ -524,10 +526,14 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     }
     const int hrj = hrow[j];
     int cai[8], hci[8];
+    {
+        const unsigned long long cw8 = *reinterpret_cast<const unsigned long long*>(&caT[8 * g]);
+        const int4 ha = *reinterpret_cast<const int4*>(&hcT[8 * g]);
+        const int4 hb = *reinterpret_cast<const int4*>(&hcT[8 * g + 4]);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        cai[b] = ca[8 * b + g];
-        hci[b] = hcol[8 * b + g];
+        for (int b = 0; b < 8; ++b) cai[b] = (int)((cw8 >> (8 * b)) & 0xffu);
+        hci[0] = ha.x; hci[1] = ha.y; hci[2] = ha.z; hci[3] = ha.w;
+        hci[4] = hb.x; hci[5] = hb.y; hci[6] = hb.z; hci[7] = hb.w;
     }
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
