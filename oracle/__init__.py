@@ -9,6 +9,8 @@ with the GPU path (``paper_1307_7820_amd``) and imports nothing from it.
 * ``r_table``: the preprocessing step of Section 3.1 that, for every pair of a
   horizontal difference vector v and a vertical difference vector v-bar,
   returns the largest running total max_k (V_k + Vbar_k) (Eq. 3).
+* ``structure``: the traceback of Section 2 through D*, the argmax of Eq. 1,
+  giving one optimal secondary structure in dot-bracket form.
 """
 
 from __future__ import annotations
@@ -126,3 +128,51 @@ def r_table(q: int, with_index: bool = False):
     if with_index:
         return R, max_idx.astype(np.uint8)
     return R
+
+
+_PAIRS = {("A", "U"), ("U", "A"), ("C", "G"), ("G", "C")}
+
+
+def structure(seq: str, table=None) -> str:
+    """One optimal secondary structure of ``seq`` as a dot-bracket string.
+
+    Section 2 keeps, beside each D(i, j), the indices D*(i, j) that attain the
+    maximum (argmax in place of max in Eq. 1) and reads the structure back from
+    D(1, n).  The argmax here is taken as a strict '>' scan takes it: the
+    first maximising term in the order of Eq. 1, i.e. the pairing term
+    b(S_i, S_j) + D(i+1, j-1) first, then the splits D(i, k) + D(k+1, j) for
+    k = i, ..., j-1.  When the pairing term wins and S_i, S_j are
+    complementary they form a pair; with b = 0 both stay unpaired.  D* is
+    recomputed from the finished table on the way back instead of stored.
+
+    ``table`` is ``fold_table(seq)`` if already computed (T[i-1, j-1] = D(i, j)).
+    """
+    n = len(seq)
+    T = fold_table(seq) if table is None else np.asarray(table)
+    s = seq.upper()
+
+    def D(i: int, j: int) -> int:  # 1-based; D(i, i-1) = D(i, i) = 0
+        return int(T[i - 1, j - 1]) if j > i else 0
+
+    out = ["."] * n
+    todo = [(1, n)] if n >= 2 else []
+    while todo:
+        i, j = todo.pop()
+        while j - i >= 1:  # at least two bases
+            v = D(i, j)
+            b = 1 if (s[i - 1], s[j - 1]) in _PAIRS else 0
+            if v == b + D(i + 1, j - 1):
+                if b:
+                    out[i - 1], out[j - 1] = "(", ")"
+                i, j = i + 1, j - 1
+                continue
+            # D(i, k) for k = i..j-1 is row i-1 of T, columns i-1..j-2 (D(i, i) = 0
+            # sits on the diagonal); D(k+1, j) is column j-1, rows i..j-1
+            splits = T[i - 1, i - 1:j - 1].astype(np.int64) + T[i:j, j - 1].astype(np.int64)
+            hits = np.flatnonzero(splits == v)
+            if hits.size == 0:
+                raise AssertionError("no term of Eq. 1 attains D(%d, %d)" % (i, j))
+            k = i + int(hits[0])
+            todo.append((k + 1, j))
+            j = k
+    return "".join(out)

@@ -8,6 +8,7 @@ j < k) and derive values from it by enumeration or by counting.
 
 from __future__ import annotations
 
+import itertools
 from typing import List
 
 import numpy as np
@@ -155,3 +156,32 @@ def lemma1_violations(T: np.ndarray) -> int:
 def reverse_table(T: np.ndarray) -> np.ndarray:
     """Table of the reversed sequence: D_rev(i, j) = D(n+1-j, n+1-i)."""
     return T[::-1, ::-1].T.copy()
+
+
+def structure_pairs(db: str) -> list:
+    """Pairs (i, j), 0-based, of a dot-bracket string; AssertionError when the
+    brackets do not match or a character is not one of '(', ')', '.'."""
+    stack, pairs = [], []
+    for x, ch in enumerate(db):
+        if ch == "(":
+            stack.append(x)
+        elif ch == ")":
+            assert stack, "')' at %d closes nothing" % x
+            pairs.append((stack.pop(), x))
+        else:
+            assert ch == ".", "bad character %r at %d" % (ch, x)
+    assert not stack, "'(' at %d is never closed" % stack[-1]
+    return pairs
+
+
+def check_structure(seq: str, db: str, score: int) -> None:
+    """A structure is a set of non-crossing complementary pairs (Section 2);
+    an optimal one has D(1, n) of them.  Matched brackets cannot cross; the
+    pairwise test checks that independently."""
+    assert len(db) == len(seq), (len(db), len(seq))
+    pairs = structure_pairs(db)
+    for i, j in pairs:
+        assert complementary(seq[i], seq[j]), (i, j, seq[i], seq[j])
+    for p, r in itertools.combinations(pairs[:200], 2):
+        assert not crosses(p, r), (p, r)
+    assert len(pairs) == score, (len(pairs), score)

@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 from paper_1307_7820_amd import gen
-from pins import (au_closed_form_table, brute_force_max, brute_force_table,
+from pins import (au_closed_form_table, brute_force_max, brute_force_table, check_structure,
                   composition_upper_bound, lemma1_violations, reverse_table)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -195,3 +195,45 @@ def test_r_index_is_first_argmax():
                 tot.append(tot[-1] + ((h >> (k - 1)) & 1) - ((c >> (k - 1)) & 1))
             assert idx[h, c] == int(np.argmax(tot))
             assert R[h, c] == max(tot)
+
+
+# ---------------------------------------------------------------- traceback pins
+# The traceback of Section 2 (D*, the argmax of Eq. 1) read back from the
+# oracle's table: pinned by hand-worked structures, by brute-force optimality
+# and by the two-letter closed form.
+
+def _golden_structures():
+    for line in open(os.path.join(GOLDEN, "structures.txt")):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        seq, db = line.split()
+        yield ("" if seq == "-" else seq), ("" if db == "-" else db)
+
+
+def test_structure_hand_cases():
+    for seq, db in _golden_structures():
+        assert oracle.structure(seq) == db, seq
+
+
+def test_structure_optimal_against_brute_force():
+    rng = np.random.default_rng([201])
+    for t in range(120):
+        n = int(rng.integers(0, 13))
+        seq = "".join(rng.choice(list("ACGU"), size=n))
+        check_structure(seq, oracle.structure(seq), brute_force_max(seq))
+
+
+def test_structure_valid_random_lengths():
+    for t, n in enumerate([2, 3, 17, 64, 65, 200, 401]):
+        seq = gen.iid_sequence(n, [202, t])
+        T = oracle.fold_table(seq)
+        check_structure(seq, oracle.structure(seq, T), int(T[0, -1]))
+
+
+def test_structure_two_letter_closed_form():
+    rng = np.random.default_rng([203])
+    for t in range(20):
+        n = int(rng.integers(1, 160))
+        seq = "".join(rng.choice(list("AU"), size=n))
+        check_structure(seq, oracle.structure(seq), min(seq.count("A"), seq.count("U")))
