@@ -157,6 +157,27 @@ def extra_n16000(nf, torch, gen, steps):
             "glookups_per_s": r.get("glookups_per_s"), "score": score, "roofline": r}
 
 
+def extra_structure(nf, gen, reps=3):
+    """Traceback through D* (nf_fold_structure) beside the fill alone
+    (nf_fold); both are synchronous host calls on the same sequence, so the
+    difference is the traceback kernel plus the n-byte structure copy."""
+    out = {}
+    for name, seq in (("n6000", gen.workload_n6000()), ("n16000", gen.workload_n16000())):
+        score, db = nf.nf_fold_structure(seq)
+        nf.nf_fold(seq)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            nf.nf_fold(seq)
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            nf.nf_fold_structure(seq)
+        t2 = time.perf_counter()
+        fold_ms, both_ms = (t1 - t0) / reps * 1e3, (t2 - t1) / reps * 1e3
+        out[name] = {"fold_ms": fold_ms, "fold_structure_ms": both_ms, "traceback_ms": both_ms - fold_ms,
+                     "pairs": score, "unpaired": db.count(".")}
+    return out
+
+
 def extra_batch(nf, torch, gen, looped_sample: int):
     seqs = gen.workload_batch4096()
     t0 = time.perf_counter()
@@ -382,6 +403,11 @@ def main():
             log("bench: batch %s" % json.dumps(extra["batch4096"]))
         except Exception as e:
             extra["batch4096"] = {"error": repr(e)}
+        try:
+            extra["structure"] = extra_structure(nf, gen)
+            log("bench: structure %s" % json.dumps(extra["structure"]))
+        except Exception as e:
+            extra["structure"] = {"error": repr(e)}
         try:
             extra["serving"] = extra_serving(nf, torch, gen)
             log("bench: serving %s" % json.dumps(extra["serving"]))

@@ -95,6 +95,21 @@ int nf_copy_R(int q, uint8_t* out, size_t cap);
  * as separate launches on two streams.  NF_MODE=staged|fused forces one. */
 int nf_fold(const char* seq, int n, int q, int16_t* S_out);
 
+/* nf_fold_structure
+ * Fold seq[0..n) and write one optimal secondary structure to db_out: n
+ * characters '(' ')' '.' (no terminator; caller-owned, at least n bytes),
+ * base i+1 pairs with base j+1 when db_out[i] = '(' matches db_out[j] = ')'.
+ * Returns D(1,n) >= 0, the number of pairs.  Synchronous.
+ *
+ * The structure is the traceback of Section 2 through D*, the argmax of
+ * Eq. 1, taken as a strict '>' scan takes it: on D(i,j) the pairing term
+ * b(S_i,S_j) + D(i+1,j-1) first (a pair when b = 1; with b = 0 both ends stay
+ * unpaired), else the split D(i,k-1) + D(k,j) with the smallest k.  So among
+ * the optimal structures one fixed one is returned.  It runs on the GPU from
+ * the finished table (one wavefront; D* is recomputed, not stored).
+ * NF_E_DEVICE if the traceback cannot complete (a table that is not Eq. 1's). */
+int nf_fold_structure(const char* seq, int n, int q, char* db_out);
+
 /* ---- Single fold (device buffers, asynchronous on a HIP stream) ----
  * d_codes: n device bytes, base codes A=0, C=1, G=2, U=3 (other values give
  *          unspecified scores but never access memory out of bounds).

@@ -84,10 +84,11 @@ int nf_copy_R(int q, uint8_t* out, size_t cap)
     return NF_OK;
 }
 
-int nf_fold(const char* seq, int n, int q, int16_t* S_out)
+// Encode seq, fill its table on the library stream and leave the plan in *out
+// (the copies and the fill are enqueued, not waited for; `padded` must live
+// until the stream is synchronised).
+static int fill_single(const char* seq, int n, int q, Plan** out, std::vector<uint8_t>& padded)
 {
-    std::lock_guard<std::recursive_mutex> lk(g_api);
-    clear_error();
     int rc = check_length(n);
     if (rc) return rc;
     if ((rc = check_q(q))) return rc;
@@ -99,11 +100,25 @@ int nf_fold(const char* seq, int n, int q, int16_t* S_out)
     Plan* p = nullptr;
     if ((rc = single_plan(n, q, &p))) return rc;
     const Geom& g = p->geom[0];
-    std::vector<uint8_t> padded(g.codes_bytes, 0);
+    padded.assign(g.codes_bytes, 0);
     std::copy(codes.begin(), codes.end(), padded.begin());
     hipStream_t s = ctx().stream;
     HIPCHK(hipMemcpyAsync((void*)p->h_folds[0].codes, padded.data(), g.codes_bytes, hipMemcpyHostToDevice, s));
     if ((rc = plan_enqueue(*p, s))) return rc;
+    *out = p;
+    return NF_OK;
+}
+
+int nf_fold(const char* seq, int n, int q, int16_t* S_out)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    Plan* p = nullptr;
+    std::vector<uint8_t> padded;
+    int rc = fill_single(seq, n, q, &p, padded);
+    if (rc) return rc;
+    const Geom& g = p->geom[0];
+    hipStream_t s = ctx().stream;
     int32_t score = 0;
     HIPCHK(hipMemcpyAsync(&score, p->d_scores.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (S_out && n > 0) {
@@ -113,6 +128,39 @@ int nf_fold(const char* seq, int n, int q, int16_t* S_out)
         HIPCHK(hipMemcpyAsync(S_out, p->d_S.p, bytes, hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
+    return score;
+}
+
+int nf_fold_structure(const char* seq, int n, int q, char* db_out)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (!db_out && n > 0) return fail(NF_E_INVAL, "db_out is NULL");
+    Plan* p = nullptr;
+    std::vector<uint8_t> padded;
+    int rc = fill_single(seq, n, q, &p, padded);
+    if (rc) return rc;
+    const Geom& g = p->geom[0];
+    hipStream_t s = ctx().stream;
+    int32_t score = 0;
+    int32_t status = 0;
+    HIPCHK(hipMemcpyAsync(&score, p->d_scores.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    std::vector<char> db(n);
+    if (n > 0) {
+        // [status: 256 B][structure: n B, rounded up to 256][spill: 2 (n/2 + 1) int2]
+        const int cap = n / 2 + 1;
+        const size_t db_off = 256, st_off = db_off + (((size_t)n + 255) & ~(size_t)255);
+        const size_t bytes = st_off + 2 * (size_t)cap * sizeof(int2);
+        if (p->d_tb.bytes < bytes && (rc = p->d_tb.alloc(bytes))) return rc;
+        char* base = (char*)p->d_tb.p;
+        HIPCHK(launch_traceback(p->h_folds[0].F, g.ld, p->h_folds[0].codes, n, (int2*)(base + st_off), cap,
+                                base + db_off, (int*)base, s));
+        HIPCHK(hipMemcpyAsync(&status, base, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(db.data(), base + db_off, n, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (status != 0) return fail(NF_E_DEVICE, "traceback stopped (status %d): no term of Eq. 1 attains a table entry", status);
+    if (n > 0) std::copy(db.begin(), db.end(), db_out);
     return score;
 }
 

@@ -115,5 +115,10 @@ hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uin
 // scores[f] = F(0, n_f)
 hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s);
 hipError_t launch_expand(const int16_t* F, int ld, int n, int16_t* S, hipStream_t s);
+// One optimal structure of the fold whose table F (leading dimension ld) and
+// codes are given, as n dot-bracket characters in db; *status = 0 on success.
+// spill: 2 * spill_cap entries of device scratch, spill_cap >= n/2 + 1.
+hipError_t launch_traceback(const int16_t* F, int ld, const uint8_t* codes, int n, int2* spill, int spill_cap,
+                            char* db, int* status, hipStream_t s);
 
 }  // namespace nf

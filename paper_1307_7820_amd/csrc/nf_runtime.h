@@ -72,6 +72,7 @@ struct Plan {
     Schedule sc;
     DevBuf arena, d_folds, d_diag, d_tile, d_btw, d_part, d_scores;
     DevBuf d_S;  // expand target for host copies of tables
+    DevBuf d_tb;  // traceback: status, structure, stack
     size_t device_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

@@ -36,7 +36,7 @@ _CODE_NAMES = {
 
 # every symbol include/nf.h declares
 EXPORTS = [
-    "nf_last_error", "nf_init", "nf_shutdown", "nf_precompute_R", "nf_copy_R", "nf_fold",
+    "nf_last_error", "nf_init", "nf_shutdown", "nf_precompute_R", "nf_copy_R", "nf_fold", "nf_fold_structure",
     "nf_fold_dev", "nf_batch_create", "nf_batch_run", "nf_batch_scores", "nf_batch_table",
     "nf_batch_info", "nf_batch_destroy", "nf_fold_batch", "nf_serve_config", "nf_fold_bytes",
     "nf_submit", "nf_poll", "nf_wait", "nf_serve_stats", "nf_autotune_q", "nf_autotune",
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "nf_precompute_R": (c_int, [c_int]),
         "nf_copy_R": (c_int, [c_int, vp, c_sz]),
         "nf_fold": (c_int, [ctypes.c_char_p, c_int, c_int, vp]),
+        "nf_fold_structure": (c_int, [ctypes.c_char_p, c_int, c_int, vp]),
         "nf_fold_dev": (c_int, [vp, c_int, c_int, vp, vp, vp]),
         "nf_batch_create": (c_int, [vp, vp, c_int, c_int, ctypes.POINTER(vp)]),
         "nf_batch_run": (c_int, [vp, vp]),
@@ -163,6 +164,16 @@ def nf_fold(seq, q: int = 0, table: bool = False):
     S = np.zeros((n, n), dtype=np.int16) if table else None
     score = _check(load().nf_fold(b, n, q, _ptr(S) if n else None))
     return (score, S) if table else score
+
+
+def nf_fold_structure(seq, q: int = 0):
+    """Fold one sequence; returns (score, structure) with the structure as a
+    dot-bracket string (the traceback through D*, see nf.h)."""
+    b = seq.encode("ascii") if isinstance(seq, str) else bytes(seq)
+    n = len(b)
+    out = ctypes.create_string_buffer(max(n, 1))
+    score = _check(load().nf_fold_structure(b, n, q, out))
+    return score, out.raw[:n].decode("ascii")
 
 
 def nf_fold_dev(d_codes, n: int, q: int = 0, d_score=None, d_S=None, stream=None) -> None:

@@ -1,0 +1,88 @@
+"""GPU parity for the traceback (nf_fold_structure).
+
+The GPU walks its own table and the oracle walks Eq. 1's, by the same argmax
+order (Section 2's D* taken with a strict '>'), so the structures must be
+identical character by character; every structure is also checked to be a
+valid optimal one (complementary, non-crossing, D(1,n) pairs).
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1307_7820_amd import gen
+from pins import check_structure
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def nf():
+    from paper_1307_7820_amd import nf as m
+    m.nf_init(0)
+    return m
+
+
+def _same(nf, seq, q=8):
+    score, db = nf.nf_fold_structure(seq, q=q)
+    T = oracle.fold_table(seq)
+    want_score = int(T[0, -1]) if len(seq) else 0
+    assert score == want_score, (len(seq), q)
+    assert db == oracle.structure(seq, T), (len(seq), q)
+    check_structure(seq, db, score)
+    return db
+
+
+def test_golden_structures(nf):
+    for line in open(os.path.join(GOLDEN, "structures.txt")):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        seq, want = line.split()
+        seq, want = ("" if seq == "-" else seq), ("" if want == "-" else want)
+        score, db = nf.nf_fold_structure(seq)
+        assert db == want, seq
+
+
+@pytest.mark.parametrize("q", range(1, 9))
+def test_sizes_all_q(nf, q):
+    for k, n in enumerate([2, 3, 17, 63, 64, 65, 129, 200, 383, 600]):
+        _same(nf, gen.iid_sequence(n, [401, q, k]), q)
+
+
+def test_structured_inputs(nf):
+    for t, s in enumerate([gen.stem_sequence(900, [402, 0]),
+                           gen.iid_sequence(700, [402, 1], probs=(0.45, 0.05, 0.05, 0.45)),
+                           "GC" * 300,            # runs of pairing terms longer than a wavefront
+                           "A" * 250 + "U" * 250,
+                           "ACGU" * 100]):
+        _same(nf, s)
+
+
+def test_n6000_equals_oracle(nf):
+    _same(nf, gen.workload_n6000())
+
+
+def test_n16000_valid(nf):
+    s = gen.workload_n16000()
+    score, db = nf.nf_fold_structure(s)
+    assert score == nf.nf_fold(s)
+    check_structure(s, db, score)
+
+
+def test_n16000_two_letter_closed_form(nf):
+    s = gen.iid_sequence(16000, [403, 0], probs=(0.5, 0.0, 0.0, 0.5))
+    score, db = nf.nf_fold_structure(s)
+    assert score == min(s.count("A"), s.count("U"))
+    check_structure(s, db, score)
+
+
+def test_repeat_calls_identical(nf):
+    s = gen.iid_sequence(3000, [404, 0])
+    first = nf.nf_fold_structure(s)
+    nf.nf_fold(gen.iid_sequence(3000, [404, 1]))  # same workspace, other contents
+    assert nf.nf_fold_structure(s) == first
