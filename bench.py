@@ -157,6 +157,29 @@ def extra_n16000(nf, torch, gen, steps):
             "glookups_per_s": r.get("glookups_per_s"), "score": score, "roofline": r}
 
 
+def extra_q_sweep(nf, torch, gen, steps=3):
+    """The n=6000 fold at every q.  At q = 1 a group holds a single split
+    point and R is the 1x1 zero table, so the same wavefront evaluates the
+    splits of Eq. 1 one by one: the plain recurrence, the ablation of the
+    Four-Russians lookup."""
+    seq = gen.workload_n6000()
+    out = {}
+    for q in range(1, 9):
+        ms, wall, score, codes = time_fold(nf, torch, seq, q, steps, 1)
+        t = ms / 1e3 / steps
+        out["q%d" % q] = {"ms_per_fold": t * 1e3, "gcups": cells(len(seq)) / t / 1e9, "score": score}
+    out["fr_speedup_q8_over_q1"] = out["q1"]["ms_per_fold"] / out["q8"]["ms_per_fold"]
+    # n = 16000, where the between-group lookups dominate: q = 1 against q = 8
+    seq = gen.workload_n16000()
+    big = {}
+    for q in (1, 8):
+        ms, wall, score, codes = time_fold(nf, torch, seq, q, 1, 1)
+        big["q%d" % q] = {"ms_per_fold": ms, "gcups": cells(len(seq)) / (ms / 1e3) / 1e9, "score": score}
+    big["fr_speedup_q8_over_q1"] = big["q1"]["ms_per_fold"] / big["q8"]["ms_per_fold"]
+    out["n16000"] = big
+    return out
+
+
 def extra_structure(nf, gen, reps=3):
     """Traceback through D* (nf_fold_structure) beside the fill alone
     (nf_fold); both are synchronous host calls on the same sequence, so the
@@ -403,6 +426,11 @@ def main():
             log("bench: batch %s" % json.dumps(extra["batch4096"]))
         except Exception as e:
             extra["batch4096"] = {"error": repr(e)}
+        try:
+            extra["q_sweep_n6000"] = extra_q_sweep(nf, torch, gen)
+            log("bench: q sweep %s" % json.dumps(extra["q_sweep_n6000"]))
+        except Exception as e:
+            extra["q_sweep_n6000"] = {"error": repr(e)}
         try:
             extra["structure"] = extra_structure(nf, gen)
             log("bench: structure %s" % json.dumps(extra["structure"]))
