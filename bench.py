@@ -180,6 +180,31 @@ def extra_q_sweep(nf, torch, gen, steps=3):
     return out
 
 
+def extra_plain_ablation(nf, torch, gen):
+    """n=16000 on staged steps, the between-group work by the lookup kernel
+    and by the plain-recurrence kernel (NF_BETWEEN=plain, packed 16-bit adds
+    and maxima, no R); per-kernel times from nf_profile_fold."""
+    seq = gen.workload_n16000()
+    n = len(seq)
+    out = {}
+    for label, env in (("lookup", {"NF_MODE": "staged"}), ("plain", {"NF_MODE": "staged", "NF_BETWEEN": "plain"})):
+        old = {k: os.environ.get(k) for k in env}
+        os.environ.update(env)
+        try:
+            ms, wall, score, codes = time_fold(nf, torch, seq, 8, 1, 1)
+            prof = nf.nf_profile_fold(codes, n, 8, 1)
+            out[label] = {"ms_per_fold": ms, "score": score,
+                          "between_ms": prof.ms[2], "tile_ms": prof.ms[1], "between_launches": prof.launches[2]}
+        finally:
+            for k, v in old.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+    out["between_speedup_lookup_over_plain"] = out["plain"]["between_ms"] / out["lookup"]["between_ms"]
+    return out
+
+
 def extra_structure(nf, gen, reps=3):
     """Traceback through D* (nf_fold_structure) beside the fill alone
     (nf_fold); both are synchronous host calls on the same sequence, so the
@@ -431,6 +456,11 @@ def main():
             log("bench: q sweep %s" % json.dumps(extra["q_sweep_n6000"]))
         except Exception as e:
             extra["q_sweep_n6000"] = {"error": repr(e)}
+        try:
+            extra["plain_ablation_n16000"] = extra_plain_ablation(nf, torch, gen)
+            log("bench: plain ablation %s" % json.dumps(extra["plain_ablation_n16000"]))
+        except Exception as e:
+            extra["plain_ablation_n16000"] = {"error": repr(e)}
         try:
             extra["structure"] = extra_structure(nf, gen)
             log("bench: structure %s" % json.dumps(extra["structure"]))

@@ -92,7 +92,11 @@ int nf_copy_R(int q, uint8_t* out, size_t cap);
  * workspace: for one fold, and for batches whose steps hold few tiles, each
  * step is one launch holding the finishes of diagonal s and the
  * between-group chunks of diagonal s+1; for larger batches the two kinds run
- * as separate launches on two streams.  NF_MODE=staged|fused forces one. */
+ * as separate launches on two streams.  NF_MODE=staged|fused forces one.
+ * NF_BETWEEN=plain (ablation only, q = 1, 2, 4, 8) computes the between-group
+ * maxima by Eq. 1's splits from the dense table instead of by R lookups, on
+ * staged steps; the table is the same.  Both are read when a workspace for
+ * (n, q) is first made and are part of its cache key. */
 int nf_fold(const char* seq, int n, int q, int16_t* S_out);
 
 /* nf_fold_structure

@@ -103,6 +103,10 @@ static_assert(sizeof(BetweenWork) == 80, "BetweenWork layout");
 hipError_t launch_stage(int q, const TileWork* titems, int ntile, const BetweenWork* bitems, int nbtw,
                         const uint8_t* R, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
+// Plain between-group maxima from the dense table (no R): the ablation of the
+// lookup.  q must give 64-post tiles (1, 2, 4, 8).
+hipError_t launch_between_plain(int q, const BetweenWork* items, int nitems, hipStream_t s, hipEvent_t e0 = nullptr,
+                                hipEvent_t e1 = nullptr);
 hipError_t launch_precompute_R(int q, uint8_t* R, hipStream_t s);
 hipError_t launch_copy_codes(const uint8_t* src, int n, uint8_t* dst, int padded, hipStream_t s);
 // With events e0/e1 the dispatch records the kernel's own start and end.

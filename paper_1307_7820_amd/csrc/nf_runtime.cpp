@@ -273,6 +273,20 @@ void build_schedule(const std::vector<int>& NTs, int target, Schedule& sc)
 // 8.19 / 14.6 ms), staged for a batch of 4096 folds (21.2 against 22.6 ms).
 constexpr long long kFusedMaxTilesPerSide = 208;
 
+bool plain_between_for(int q)
+{
+    const char* e = getenv("NF_BETWEEN");
+    return e && strcmp(e, "plain") == 0 && tile_size(q) == 64;
+}
+
+// The between launch of a staged step: the lookup kernel, or the plain one.
+static hipError_t launch_btw(const Plan& p, const BetweenWork* items, int nitems, const uint8_t* R, hipStream_t s,
+                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+{
+    return p.plain ? launch_between_plain(p.q, items, nitems, s, e0, e1)
+                   : launch_between(p.q, items, nitems, R, s, e0, e1);
+}
+
 int plan_mode_for(const std::vector<int>& NTs)
 {
     if (const char* e = getenv("NF_MODE")) {  // read per plan: cached plans keep their mode
@@ -430,7 +444,7 @@ int plan_enqueue_direct(Plan& p, hipStream_t s)
         }
         HIPCHK(hipStreamWaitEvent(s2, ev_tile, 0));  // finish(sg-1) done
         if (sc.btw_cnt[sg] > 0)
-            HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R, s2));
+            HIPCHK(launch_btw(p, (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R, s2));
         HIPCHK(hipEventRecord(ev_btw, s2));
     }
     // join the side stream back into s
@@ -530,7 +544,7 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
                 }
                 if (sc.btw_cnt[sg] > 0) {
                     if (!pair(a, b)) return fail(NF_E_DEVICE, "event creation failed");
-                    HIPCHK(launch_between(p.q, bw, sc.btw_cnt[sg], R, s, a, b));
+                    HIPCHK(launch_btw(p, bw, sc.btw_cnt[sg], R, s, a, b));
                     recs.push_back({2, a, b, btw_lk[sg], 0.0, 0.0});
                 }
             }
@@ -589,6 +603,8 @@ int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out)
         NTs.push_back(p->geom.back().NT);
     }
     p->mode = plan_mode_for(NTs);
+    p->plain = plain_between_for(q);
+    if (p->plain) p->mode = kModeStaged;  // the fused step has the lookup built in
     build_schedule(NTs, between_target(p->mode), p->sc);
     int rc = plan_allocate(*p);
     if (rc) return rc;
@@ -600,7 +616,10 @@ int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out)
 int single_plan(int n, int q, Plan** out)
 {
     Context& c = ctx();
-    const long long key = (long long)n * 16 + q;
+    // NF_MODE and NF_BETWEEN are read when a plan is made, so they are part of the key
+    const char* me = getenv("NF_MODE");
+    const int mode_env = !me ? 0 : strcmp(me, "fused") == 0 ? 1 : strcmp(me, "staged") == 0 ? 2 : 0;
+    const long long key = (((long long)n * 16 + q) * 2 + (plain_between_for(q) ? 1 : 0)) * 3 + mode_env;
     for (auto it = c.plans.begin(); it != c.plans.end(); ++it) {
         if (it->first == key) {
             auto ent = std::move(*it);

@@ -67,6 +67,7 @@ enum PlanMode { kModeStaged = 0, kModeFused = 1 };
 struct Plan {
     int q = 8;
     int mode = kModeStaged;
+    bool plain = false;  // between-group work by the plain recurrence (NF_BETWEEN=plain)
     std::vector<Geom> geom;
     std::vector<FoldDesc> h_folds;
     Schedule sc;
@@ -117,6 +118,10 @@ BetweenWork to_work(const BetweenItem& it, const std::vector<FoldDesc>& fd, int3
 int plan_enqueue(Plan& p, hipStream_t s);
 int plan_enqueue_direct(Plan& p, hipStream_t s);
 int plan_mode_for(const std::vector<int>& NTs);
+// NF_BETWEEN=plain: the between-group work of new plans runs the plain
+// recurrence (k_between_plain, the ablation of the lookup) on staged steps;
+// only for 64-post tiles (q = 1, 2, 4, 8), ignored otherwise.
+bool plain_between_for(int q);
 int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out);
 int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out);
 int single_plan(int n, int q, Plan** out);
