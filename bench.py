@@ -393,7 +393,20 @@ def run_only(args, torch, gen, nf):
         torch.cuda.synchronize()
         print(json.dumps({"only": "batch", "count": len(seqs), "checksum": int(b.scores().sum())}))
         return
-    seq = gen.workload_n6000() if args.only == "n6000" else gen.workload_n16000()
+    if args.only in ("structure6000", "structure16000"):
+        # fill + traceback through D* (nf_fold_structure), K times
+        seq = gen.workload_n6000() if args.only == "structure6000" else gen.workload_n16000()
+        for _ in range(args.warmup + args.steps):
+            score, db = nf.nf_fold_structure(seq, q=args.q if args.q else 8)
+        print(json.dumps({"only": args.only, "n": len(seq), "pairs": score}))
+        return
+    if args.only == "plain16000":
+        # n=16000 on staged steps with the plain-recurrence between kernel
+        os.environ["NF_MODE"] = "staged"
+        os.environ["NF_BETWEEN"] = "plain"
+        seq = gen.workload_n16000()
+    else:
+        seq = gen.workload_n6000() if args.only == "n6000" else gen.workload_n16000()
     q = args.q if args.q else 8
     ms, wall, score, _ = time_fold(nf, torch, seq, q, args.steps, args.warmup)
     print(json.dumps({"only": args.only, "n": len(seq), "q": q, "ms_per_fold": ms / args.steps,
@@ -408,7 +421,8 @@ def main():
     ap.add_argument("--q", type=int, default=0)
     ap.add_argument("--cpu-budget-s", type=float, default=10.0)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra workloads)")
-    ap.add_argument("--only", choices=["n6000", "n16000", "batch", "copy"],
+    ap.add_argument("--only", choices=["n6000", "n16000", "batch", "copy", "structure6000", "structure16000",
+                                       "plain16000"],
                     help="run one workload K times and print a short line (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
