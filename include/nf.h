@@ -22,7 +22,7 @@
  *    the next call on that thread).
  *  - Sequences: n bytes of 'A','C','G','U' (lower case accepted); any other
  *    byte (including 'T' and 'N') is NF_E_INVAL.  0 <= n <= NF_MAX_N.
- *  - q: 1..8, or 0 to let the library choose (autotuned value, else 8).
+ *  - q: 1..9, or 0 to let the library choose (autotuned value, else 8).
  *  - Table layout (S_out, row-major n*n int16, caller-owned):
  *        S_out[i*n + j] = D(i+1, j+1) for i <= j, and 0 for i > j.
  *  - Inputs are borrowed for the duration of the call (nf_submit copies);
@@ -57,7 +57,7 @@ enum {
 /* Scores are at most n/2 and are stored in int16 tables. */
 #define NF_MAX_N 65534
 #define NF_Q_MIN 1
-#define NF_Q_MAX 8
+#define NF_Q_MAX 9
 
 /* Message for the last negative return on the calling thread ("" if none). */
 const char* nf_last_error(void);

@@ -792,6 +792,7 @@ hipError_t dispatch(int q, int which, const void* items, int nitems, const uint8
     case 6: return launch_q<6>(which, items, nitems, R, s, e0, e1);
     case 7: return launch_q<7>(which, items, nitems, R, s, e0, e1);
     case 8: return launch_q<8>(which, items, nitems, R, s, e0, e1);
+    case 9: return launch_q<9>(which, items, nitems, R, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -800,7 +801,7 @@ hipError_t dispatch(int q, int which, const void* items, int nitems, const uint8
 
 hipError_t launch_precompute_R(int q, uint8_t* R, hipStream_t s)
 {
-    if (q < 1 || q > 8) return hipErrorInvalidValue;
+    if (q < 1 || q > 9) return hipErrorInvalidValue;
     const int entries = 1 << (2 * (q - 1));
     hipLaunchKernelGGL(k_precompute_R, dim3((entries + 255) / 256), dim3(256), 0, s, q, R);
     return hipGetLastError();
@@ -859,6 +860,7 @@ hipError_t launch_stage(int q, const TileWork* titems, int ntile, const BetweenW
     case 6: return stage_q<6>(titems, ntile, bitems, nbtw, R, s, e0, e1);
     case 7: return stage_q<7>(titems, ntile, bitems, nbtw, R, s, e0, e1);
     case 8: return stage_q<8>(titems, ntile, bitems, nbtw, R, s, e0, e1);
+    case 9: return stage_q<9>(titems, ntile, bitems, nbtw, R, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }

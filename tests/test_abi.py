@@ -39,16 +39,16 @@ def test_rejects_bad_input_without_device(lib):
     # validation happens before any device call
     assert lib.nf_fold(b"ACGT", 4, 0, None) == nf.NF_E_INVAL
     assert "0x54" in nf.last_error()
-    assert lib.nf_fold(b"ACGU", 4, 9, None) == nf.NF_E_INVAL
+    assert lib.nf_fold(b"ACGU", 4, 10, None) == nf.NF_E_INVAL
     assert lib.nf_fold(b"ACGU", -1, 0, None) == nf.NF_E_INVAL
     buf = ctypes.create_string_buffer(8)
     assert lib.nf_fold_structure(b"ACGU", 4, 0, None) == nf.NF_E_INVAL  # no output buffer
     assert lib.nf_fold_structure(b"ACGX", 4, 0, buf) == nf.NF_E_INVAL
-    assert lib.nf_fold_structure(b"ACGU", 4, 9, buf) == nf.NF_E_INVAL
+    assert lib.nf_fold_structure(b"ACGU", 4, 10, buf) == nf.NF_E_INVAL
     assert buf.raw == b"\0" * 8  # nothing written on error
     assert lib.nf_fold(b"A", nf.NF_MAX_N + 1, 0, None) == nf.NF_E_TOOLONG
     assert lib.nf_precompute_R(0) == nf.NF_E_INVAL
-    assert lib.nf_precompute_R(9) == nf.NF_E_INVAL
+    assert lib.nf_precompute_R(10) == nf.NF_E_INVAL
     buf = (ctypes.c_uint8 * 4)()
     assert lib.nf_copy_R(3, ctypes.addressof(buf), 4) == nf.NF_E_INVAL  # needs 16 bytes
 

@@ -28,7 +28,7 @@ def _fold_both(nf, s, q):
     return score, T, want
 
 
-@pytest.mark.parametrize("q", range(1, 9))
+@pytest.mark.parametrize("q", range(1, 10))
 def test_R_table(nf, q):
     got = nf.nf_copy_R(q)
     assert np.array_equal(got, oracle.r_table(q))
@@ -46,7 +46,7 @@ def test_trivial_lengths(nf):
 SIZES = [2, 3, 5, 17, 62, 63, 64, 65, 127, 128, 129, 200, 255, 256, 257, 320, 383, 449, 511, 600]
 
 
-@pytest.mark.parametrize("q", range(1, 9))
+@pytest.mark.parametrize("q", range(1, 10))
 def test_full_tables_all_q(nf, q):
     for k, n in enumerate(SIZES):
         s = gen.iid_sequence(n, [101, q, k])
@@ -59,7 +59,7 @@ def test_full_tables_all_q(nf, q):
 def test_n500_every_q(nf):
     s = gen.workload_n500()
     want = oracle.fold_table(s)
-    for q in range(1, 9):
+    for q in range(1, 10):
         score, T = nf.nf_fold(s, q=q, table=True)
         assert np.array_equal(T, want), q
         assert score == int(want[0, -1])
