@@ -86,3 +86,13 @@ def test_repeat_calls_identical(nf):
     first = nf.nf_fold_structure(s)
     nf.nf_fold(gen.iid_sequence(3000, [404, 1]))  # same workspace, other contents
     assert nf.nf_fold_structure(s) == first
+
+
+def test_max_length_two_letter_closed_form(nf):
+    # the longest input the ABI accepts (12 GB of device workspace): the score
+    # and a structure with min(#A, #U) pairs, pinned by the closed form
+    n = nf.NF_MAX_N
+    s = gen.iid_sequence(n, [405, 0], probs=(0.5, 0.0, 0.0, 0.5))
+    score, db = nf.nf_fold_structure(s)
+    assert score == min(s.count("A"), s.count("U"))
+    check_structure(s, db, score)
