@@ -46,3 +46,20 @@ def test_n6000_table(nf):
     s = gen.workload_n6000()
     score, T = nf.nf_fold(s, q=8, table=True)
     assert np.array_equal(T, oracle.fold_table(s))
+
+
+def test_plain_runs_staged_steps(nf):
+    # NF_BETWEEN=plain makes a new workspace that runs staged steps (the fused
+    # step has the lookup built in): between launches, no fused launches,
+    # although a single fold would otherwise run fused steps
+    import torch
+    s = gen.iid_sequence(3000, [503, 0])
+    codes = torch.from_numpy(nf.encode(s)).cuda()
+    prof = nf.nf_profile_fold(codes, len(s), 8, 1)
+    assert prof.launches[2] > 0 and prof.launches[3] == 0
+    os.environ.pop("NF_BETWEEN")
+    try:
+        prof = nf.nf_profile_fold(codes, len(s), 8, 1)
+        assert prof.launches[3] > 0  # the lookup workspace for the same (n, q)
+    finally:
+        os.environ["NF_BETWEEN"] = "plain"
