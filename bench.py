@@ -40,6 +40,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def splits(n: int) -> float:
+    """Split evaluations of plain Eq. 1 over the whole table, (n-1)n(n+1)/6:
+    the inner-loop count of the plain recurrence, a method-independent rate."""
+    return (n - 1) * n * (n + 1) / 6.0
+
+
 def cells(n: int) -> float:
     return n * (n + 1) / 2.0
 
@@ -154,6 +160,7 @@ def extra_n16000(nf, torch, gen, steps):
     t = ms / 1e3 / steps
     r = roofline(nf, codes, len(seq), 8, reps=1)
     return {"n": 16000, "q": 8, "ms_per_fold": t * 1e3, "gcups": cells(16000) / t / 1e9,
+            "split_equivalent_gsps": splits(16000) / t / 1e9,
             "glookups_per_s": r.get("glookups_per_s"), "score": score, "roofline": r}
 
 
@@ -489,6 +496,7 @@ def main():
         "metric": "Nussinov GCUPS at n=6000/16000; batched folds/s + p99 latency vs plain",
         "value": value, "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "split_equivalent_gsps": splits(n) / (ms_per / 1e3) / 1e9,
         "dtype": "int16", "data": "synthetic",
         "config": {"workload": "single iid uniform ACGU sequence, n=6000, two-vector Four-Russians fill",
                    "n": n, "q": q, "tile": roof.get("tile"), "score": score},
