@@ -251,6 +251,12 @@ def extra_batch(nf, torch, gen, looped_sample: int):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     scores = b.scores()
+    # structures of all 4096 folds (nf_batch_structures: one traceback
+    # workgroup per fold, host call including the copies)
+    b.structures()
+    t0 = time.perf_counter()
+    dbs = b.structures()
+    structures_ms = (time.perf_counter() - t0) * 1e3
     b.close()
     # looped single-fold kernel on a sample of the same sequences (device codes,
     # plans warmed first), extrapolated to all 4096
@@ -273,7 +279,8 @@ def extra_batch(nf, torch, gen, looped_sample: int):
             "gcups": tot_cells / (ms / 1e3) / 1e9, "prepare_s": prep,
             "looped_sample": len(idx), "looped_ms_sample": loop_ms,
             "looped_est_ms_all": looped_est_ms, "looped_folds_per_s": len(seqs) / (looped_est_ms / 1e3),
-            "speedup_vs_looped": looped_est_ms / ms, "score_checksum": int(scores.sum())}
+            "speedup_vs_looped": looped_est_ms / ms, "score_checksum": int(scores.sum()),
+            "structures_ms": structures_ms, "structure_pairs": sum(db.count("(") for db in dbs)}
 
 
 def _pct(xs, p):

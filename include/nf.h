@@ -142,6 +142,12 @@ int nf_batch_run(nf_batch* b, void* stream);
 int nf_batch_scores(nf_batch* b, int32_t* scores_out);
 /* Wait for the last run and copy the table of sequence idx (ns[idx]^2 int16). */
 int nf_batch_table(nf_batch* b, int idx, int16_t* S_out);
+/* One optimal structure per fold of a run batch, as nf_fold_structure gives
+ * it (Section 2, the traceback through D* with the same tie rule), all folds
+ * traced back at once (one workgroup per fold).  db_outs[i] receives n_i
+ * characters (no terminator); a NULL entry skips that fold.  NF_E_INVAL if
+ * the batch has not been run. */
+int nf_batch_structures(nf_batch* b, char* const* db_outs);
 /* Number of sequences and total device bytes the batch holds. */
 int nf_batch_info(const nf_batch* b, int* count, size_t* device_bytes);
 void nf_batch_destroy(nf_batch* b);

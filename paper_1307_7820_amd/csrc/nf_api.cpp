@@ -272,6 +272,70 @@ int nf_batch_table(nf_batch* b, int idx, int16_t* S_out)
     return NF_OK;
 }
 
+int nf_batch_structures(nf_batch* b, char* const* db_outs)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (!b || !db_outs) return fail(NF_E_INVAL, "NULL argument");
+    if (!b->ran) return fail(NF_E_INVAL, "batch has not been run");
+    HIPCHK(hipEventSynchronize(b->done));
+    Plan& p = *b->plan;
+    const int count = (int)b->ns.size();
+    std::vector<int> idx;  // folds that get a structure
+    size_t db_total = 0, sp_total = 0;
+    for (int i = 0; i < count; ++i) {
+        if (!db_outs[i] || b->ns[i] == 0) continue;
+        idx.push_back(i);
+        db_total += (size_t)b->ns[i];
+        sp_total += 2 * (size_t)(b->ns[i] / 2 + 1);
+    }
+    if (idx.empty()) return NF_OK;
+    // [work: one TracebackWork per fold][status: one int per fold][structures][spill]
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t nw = idx.size();
+    const size_t st_off = up(nw * sizeof(TracebackWork));
+    const size_t db_off = st_off + up(nw * sizeof(int));
+    const size_t sp_off = db_off + up(db_total);
+    const size_t bytes = sp_off + sp_total * sizeof(int2);
+    int rc;
+    if (p.d_tb.bytes < bytes && (rc = p.d_tb.alloc(bytes))) return rc;
+    char* base = (char*)p.d_tb.p;
+    std::vector<TracebackWork> work(nw);
+    size_t dbo = 0, spo = 0;
+    for (size_t k = 0; k < nw; ++k) {
+        const int i = idx[k], n = b->ns[i];
+        TracebackWork& w = work[k];
+        w.F = p.h_folds[i].F;
+        w.codes = p.h_folds[i].codes;
+        w.ld = p.geom[i].ld;
+        w.n = n;
+        w.spill_cap = n / 2 + 1;
+        w.spill = (int2*)(base + sp_off) + spo;
+        w.db = base + db_off + dbo;
+        w.status = (int*)(base + st_off) + k;
+        dbo += (size_t)n;
+        spo += 2 * (size_t)w.spill_cap;
+    }
+    hipStream_t s = ctx().stream;
+    std::vector<int> status(nw, 0);
+    std::vector<char> db(db_total);
+    HIPCHK(hipMemcpyAsync(base, work.data(), nw * sizeof(TracebackWork), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_traceback_many((const TracebackWork*)base, (int)nw, s));
+    HIPCHK(hipMemcpyAsync(status.data(), base + st_off, nw * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(db.data(), base + db_off, db_total, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (size_t k = 0; k < nw; ++k)
+        if (status[k] != 0)
+            return fail(NF_E_DEVICE, "traceback of fold %d stopped (status %d)", idx[k], status[k]);
+    dbo = 0;
+    for (size_t k = 0; k < nw; ++k) {
+        const int n = b->ns[idx[k]];
+        std::copy(db.begin() + dbo, db.begin() + dbo + n, db_outs[idx[k]]);
+        dbo += (size_t)n;
+    }
+    return NF_OK;
+}
+
 int nf_batch_info(const nf_batch* b, int* count, size_t* device_bytes)
 {
     clear_error();

@@ -124,5 +124,16 @@ hipError_t launch_expand(const int16_t* F, int ld, int n, int16_t* S, hipStream_
 // spill: 2 * spill_cap entries of device scratch, spill_cap >= n/2 + 1.
 hipError_t launch_traceback(const int16_t* F, int ld, const uint8_t* codes, int n, int2* spill, int spill_cap,
                             char* db, int* status, hipStream_t s);
+// The same for many folds at once, one workgroup per entry of work (device).
+struct TracebackWork {
+    const int16_t* F;
+    const uint8_t* codes;
+    int2* spill;   // 2 * spill_cap entries, spill_cap >= n/2 + 1
+    char* db;      // n bytes
+    int* status;
+    long long ld;
+    int n, spill_cap;
+};
+hipError_t launch_traceback_many(const TracebackWork* work, int count, hipStream_t s);
 
 }  // namespace nf

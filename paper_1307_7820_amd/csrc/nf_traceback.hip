@@ -30,10 +30,9 @@ namespace {
 constexpr int kTbWaves = 16;
 constexpr int kFront = 2048;
 
-__global__ __launch_bounds__(kTbWaves * 64) void k_traceback(const int16_t* __restrict__ F, long long ld,
-                                                             const uint8_t* __restrict__ codes, int n,
-                                                             int2* __restrict__ spill, int spill_cap,
-                                                             char* __restrict__ db, int* __restrict__ status)
+__device__ __forceinline__ void traceback_body(const int16_t* __restrict__ F, long long ld,
+                                               const uint8_t* __restrict__ codes, int n, int2* __restrict__ spill,
+                                               int spill_cap, char* __restrict__ db, int* __restrict__ status)
 {
     __shared__ int2 front[2][kFront];
     __shared__ int count[2];
@@ -140,6 +139,21 @@ __global__ __launch_bounds__(kTbWaves * 64) void k_traceback(const int16_t* __re
     if (tid == 0) *status = fail ? fail : (levels > n ? 1 : 0);
 }
 
+__global__ __launch_bounds__(kTbWaves * 64) void k_traceback(const int16_t* __restrict__ F, long long ld,
+                                                             const uint8_t* __restrict__ codes, int n,
+                                                             int2* __restrict__ spill, int spill_cap,
+                                                             char* __restrict__ db, int* __restrict__ status)
+{
+    traceback_body(F, ld, codes, n, spill, spill_cap, db, status);
+}
+
+// One workgroup per fold of a batch.
+__global__ __launch_bounds__(kTbWaves * 64) void k_traceback_many(const TracebackWork* __restrict__ work)
+{
+    const TracebackWork& w = work[blockIdx.x];
+    traceback_body(w.F, w.ld, w.codes, w.n, w.spill, w.spill_cap, w.db, w.status);
+}
+
 }  // namespace
 
 hipError_t launch_traceback(const int16_t* F, int ld, const uint8_t* codes, int n, int2* spill, int spill_cap,
@@ -148,6 +162,13 @@ hipError_t launch_traceback(const int16_t* F, int ld, const uint8_t* codes, int 
     if (n < 0 || ld < n + 1 || spill_cap < n / 2 + 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_traceback, dim3(1), dim3(kTbWaves * 64), 0, s, F, (long long)ld, codes, n, spill,
                        spill_cap, db, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_traceback_many(const TracebackWork* work, int count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_traceback_many, dim3(count), dim3(kTbWaves * 64), 0, s, work);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ _CODE_NAMES = {
 EXPORTS = [
     "nf_last_error", "nf_init", "nf_shutdown", "nf_precompute_R", "nf_copy_R", "nf_fold", "nf_fold_structure",
     "nf_fold_dev", "nf_batch_create", "nf_batch_run", "nf_batch_scores", "nf_batch_table",
-    "nf_batch_info", "nf_batch_destroy", "nf_fold_batch", "nf_serve_config", "nf_fold_bytes",
+    "nf_batch_info", "nf_batch_structures", "nf_batch_destroy", "nf_fold_batch", "nf_serve_config", "nf_fold_bytes",
     "nf_submit", "nf_poll", "nf_wait", "nf_serve_stats", "nf_autotune_q", "nf_autotune",
     "nf_profile_fold",
 ]
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "nf_batch_run": (c_int, [vp, vp]),
         "nf_batch_scores": (c_int, [vp, vp]),
         "nf_batch_table": (c_int, [vp, c_int, vp]),
+        "nf_batch_structures": (c_int, [vp, vp]),
         "nf_batch_info": (c_int, [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_sz)]),
         "nf_batch_destroy": (None, [vp]),
         "nf_fold_batch": (c_int, [vp, vp, c_int, c_int, vp, vp]),
@@ -229,6 +230,13 @@ class Batch:
         out = np.zeros((n, n), dtype=np.int16)
         _check(load().nf_batch_table(self._h, idx, out.ctypes.data if n else None))
         return out
+
+    def structures(self) -> list:
+        """One optimal dot-bracket structure per fold (nf_batch_structures)."""
+        bufs = [ctypes.create_string_buffer(max(1, n)) for n in self.ns]
+        ptrs = (ctypes.c_void_p * max(1, self.count))(*[ctypes.addressof(b) for b in bufs])
+        _check(load().nf_batch_structures(self._h, ctypes.cast(ptrs, ctypes.c_void_p)))
+        return [b.raw[:n].decode("ascii") for b, n in zip(bufs, self.ns)]
 
     def device_bytes(self) -> int:
         c = ctypes.c_int()

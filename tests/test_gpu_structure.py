@@ -96,3 +96,30 @@ def test_max_length_two_letter_closed_form(nf):
     score, db = nf.nf_fold_structure(s)
     assert score == min(s.count("A"), s.count("U"))
     check_structure(s, db, score)
+
+
+def test_batch_structures_equal_oracle_and_alone(nf):
+    rng = np.random.default_rng([406])
+    seqs = [gen.iid_sequence(int(rng.integers(0, 700)), [407, t]) for t in range(60)]
+    seqs += ["", "A", "AU", "GGGAAACCC"]
+    b = nf.Batch(seqs, q=8)
+    b.run()
+    dbs = b.structures()
+    for s, db in zip(seqs, dbs):
+        assert db == oracle.structure(s), len(s)
+        if s:
+            assert db == nf.nf_fold_structure(s, q=8)[1], len(s)
+    b.close()
+
+
+def test_batch4096_structures_valid(nf):
+    seqs = gen.workload_batch4096()
+    b = nf.Batch(seqs, q=8)
+    b.run()
+    scores = b.scores()
+    dbs = b.structures()
+    for k in range(0, len(seqs), 37):
+        check_structure(seqs[k], dbs[k], int(scores[k]))
+    for k in (0, 1000, 4095):
+        assert dbs[k] == oracle.structure(seqs[k]), k
+    b.close()
