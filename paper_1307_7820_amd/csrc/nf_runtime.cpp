@@ -2,6 +2,7 @@
 // fold plans (workspace + packed wavefront schedule + captured HIP graph),
 // prepared batches, the serving engine and the q autotuner.
 #include "nf.h"
+#include "nf_test.h"
 #include "nf_internal.h"
 #include "nf_runtime.h"
 
@@ -15,7 +16,9 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
+#include <tuple>
 #include <vector>
 
 namespace nf {
@@ -752,3 +755,117 @@ int autotune_run(int n, int qmin, int qmax, int reps)
 }
 
 }  // namespace nf
+
+// ------------------------------------------------------------------ test hook
+
+namespace nf {
+namespace {
+
+// Check the invariants of build_schedule for folds of NT[f] tiles per side;
+// "" when they hold, else the first violation.
+std::string check_schedule(const std::vector<int>& NTs, int target)
+{
+    Schedule sc;
+    build_schedule(NTs, target, sc);
+    char buf[256];
+    auto bad = [&](const char* fmt, long long a, long long b, long long c) {
+        snprintf(buf, sizeof buf, fmt, a, b, c);
+        return std::string(buf);
+    };
+    int stages = 0;
+    for (int v : NTs) stages = std::max(stages, v);
+    if (sc.stages != stages) return bad("stages %lld, expected %lld%.0lld", sc.stages, stages, 0);
+    const int nf = (int)NTs.size();
+    // main-diagonal tiles: each (f, A) once
+    std::vector<std::vector<int>> seen(nf);
+    for (int f = 0; f < nf; ++f) seen[f].assign(NTs[f], 0);
+    for (const TileItem& it : sc.diag) {
+        if (it.fold < 0 || it.fold >= nf || it.A < 0 || it.A >= NTs[it.fold] || it.d != 0)
+            return bad("bad diagonal item fold %lld A %lld d %lld", it.fold, it.A, it.d);
+        if (seen[it.fold][it.A]++) return bad("diagonal tile (%lld, %lld) twice%.0lld", it.fold, it.A, 0);
+    }
+    for (int f = 0; f < nf; ++f)
+        for (int A = 0; A < NTs[f]; ++A)
+            if (!seen[f][A]) return bad("diagonal tile (%lld, %lld) missing%.0lld", f, A, 0);
+    // between items, by (fold, A, d): the groups C in [A+2, A+d-1) exactly once,
+    // in the stage d-1, one slot per tile, atomic iff several items
+    std::map<std::tuple<int, int, int>, std::vector<const BetweenItem*>> btw;
+    for (int sg = 0; sg < stages; ++sg) {
+        std::set<int> slots_of_stage;
+        std::map<int, std::tuple<int, int, int>> owner;
+        for (int k = sc.btw_off[sg]; k < sc.btw_off[sg] + sc.btw_cnt[sg]; ++k) {
+            const BetweenItem& it = sc.btw[k];
+            if (it.d != sg + 1) return bad("between item of stage %lld has d = %lld%.0lld", sg, it.d, 0);
+            const int half = (sg & 1) * sc.max_slots;
+            if (it.slot < half || it.slot >= half + sc.max_slots)
+                return bad("stage %lld slot %lld outside its half (max_slots %lld)", sg, it.slot, sc.max_slots);
+            auto key = std::make_tuple(it.fold, it.A, it.d);
+            auto o = owner.find(it.slot);
+            if (o != owner.end() && o->second != key) return bad("stage %lld: slot %lld shared by two tiles%.0lld", sg, it.slot, 0);
+            owner[it.slot] = key;
+            btw[key].push_back(&it);
+        }
+    }
+    for (int f = 0; f < nf; ++f)
+        for (int d = 1; d < NTs[f]; ++d)
+            for (int A = 0; A + d < NTs[f]; ++A) {
+                auto itv = btw.find(std::make_tuple(f, A, d));
+                if (d < 4) {
+                    if (itv != btw.end()) return bad("tile d = %lld (fold %lld) has between items%.0lld", d, f, 0);
+                    continue;
+                }
+                if (itv == btw.end()) return bad("tile (%lld, %lld, d = %lld) has no between items", f, A, d);
+                std::vector<int> cover(NTs[f], 0);
+                const int slot = itv->second[0]->slot;
+                for (const BetweenItem* it : itv->second) {
+                    if (it->slot != slot) return bad("tile (%lld, %lld): items in two slots%.0lld", f, A, 0);
+                    if (it->pad0 != (itv->second.size() > 1 ? 1 : 0))
+                        return bad("tile (%lld, %lld): atomic flag %lld", f, A, it->pad0);
+                    for (int C = it->c0; C < it->c1; ++C) {
+                        if (C < A + 2 || C > A + d - 2) return bad("tile (%lld, %lld): group tile C = %lld outside (A+1, B-1)", f, A, C);
+                        cover[C]++;
+                    }
+                }
+                for (int C = A + 2; C <= A + d - 2; ++C)
+                    if (cover[C] != 1) return bad("tile (%lld, %lld): C = %lld not covered exactly once", f, A, C);
+            }
+    // tile finishes: every (f, A, d >= 1) once, at stage d, reading its slot
+    for (int f = 0; f < nf; ++f) seen[f].assign(NTs[f] * (size_t)NTs[f], 0);
+    for (int sg = 1; sg < stages; ++sg) {
+        std::set<int> slots;
+        for (int k = sc.tile_off[sg]; k < sc.tile_off[sg] + sc.tile_cnt[sg]; ++k) {
+            const TileItem& it = sc.tile[k];
+            if (it.d != sg || it.fold < 0 || it.fold >= nf || it.A < 0 || it.A + it.d >= NTs[it.fold])
+                return bad("bad tile item at stage %lld (A %lld, d %lld)", sg, it.A, it.d);
+            if (seen[it.fold][(size_t)it.A * NTs[it.fold] + it.d]++) return bad("tile (%lld, %lld, %lld) twice", it.fold, it.A, it.d);
+            if (it.d < 4) {
+                if (it.nslot != 0) return bad("tile d = %lld reads a slot%.0lld%.0lld", it.d, 0, 0);
+                continue;
+            }
+            auto itv = btw.find(std::make_tuple(it.fold, it.A, it.d));
+            if (it.nslot != 1 || itv == btw.end() || it.slot0 != itv->second[0]->slot)
+                return bad("tile (%lld, %lld, %lld) reads the wrong slot", it.fold, it.A, it.d);
+            if (!slots.insert(it.slot0).second) return bad("stage %lld: two tiles read slot %lld%.0lld", sg, it.slot0, 0);
+        }
+    }
+    for (int f = 0; f < nf; ++f)
+        for (int A = 0; A < NTs[f]; ++A)
+            for (int d = 1; A + d < NTs[f]; ++d)
+                if (!seen[f][(size_t)A * NTs[f] + d]) return bad("tile (%lld, %lld, %lld) missing", f, A, d);
+    return "";
+}
+
+}  // namespace
+}  // namespace nf
+
+// Test hook (include/nf_test.h): host-only check of the wavefront schedule.
+extern "C" int nf_test_schedule(const int* NTs, int count, int target, char* msg, int cap)
+{
+    if (count < 0 || (count > 0 && !NTs) || target < 1) return NF_E_INVAL;
+    std::vector<int> v(NTs, NTs + count);
+    for (int x : v)
+        if (x < 1) return NF_E_INVAL;
+    const std::string err = nf::check_schedule(v, target);
+    if (msg && cap > 0) snprintf(msg, (size_t)cap, "%s", err.c_str());
+    return err.empty() ? NF_OK : 1;
+}

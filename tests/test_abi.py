@@ -61,3 +61,38 @@ def test_fold_bytes_is_host_arithmetic(lib):
     assert 650e6 < b8 < 800e6
     assert nf.nf_fold_bytes(100, 8) < nf.nf_fold_bytes(1000, 8)
     assert nf.nf_fold_bytes(-1, 8) == 0
+
+
+def _check_schedule(lib, nts, target):
+    arr = (ctypes.c_int * len(nts))(*nts)
+    msg = ctypes.create_string_buffer(256)
+    rc = lib.nf_test_schedule(arr, len(nts), target, msg, 256)
+    assert rc == 0, (nts[:8], target, msg.value.decode())
+
+
+def test_schedule_invariants_single_folds(lib):
+    # one fold of NT tiles per side (n + 1 <= 64 NT), chunk targets from one
+    # chunk per tile-pair up to whole tiles
+    for nt in [1, 2, 3, 4, 5, 6, 9, 17, 40, 94, 251]:
+        for target in [1, 7, 64, 1024, 1 << 20]:
+            _check_schedule(lib, [nt], target)
+
+
+def test_schedule_invariants_batches(lib):
+    import numpy as np
+    rng = np.random.default_rng([601])
+    for t in range(30):
+        count = int(rng.integers(1, 60))
+        nts = [int(x) for x in rng.integers(1, 40, size=count)]
+        _check_schedule(lib, nts, int(rng.choice([1, 5, 100, 1024])))
+    # the 4096-fold workload's tile counts (n log-uniform in [50, 2000], 64-post tiles)
+    from paper_1307_7820_amd import gen
+    nts = [(len(s) + 1 + 63) // 64 for s in gen.workload_batch4096()]
+    _check_schedule(lib, nts, 1024)
+
+
+def test_schedule_hook_rejects_bad_input(lib):
+    from paper_1307_7820_amd import nf
+    arr = (ctypes.c_int * 2)(3, 0)
+    assert lib.nf_test_schedule(arr, 2, 1024, None, 0) == nf.NF_E_INVAL
+    assert lib.nf_test_schedule(arr, 1, 0, None, 0) == nf.NF_E_INVAL
