@@ -170,15 +170,24 @@ int nf_fold_batch(const char* const* seqs, const int* ns, int count, int q,
 int nf_serve_config(size_t hbm_budget_bytes, int max_slots, int max_queue);
 
 /* Device bytes a fold of length n holds while active in the serving engine
- * under q (table, packed words, accumulators; a request with want_table holds
- * n*n*2 more).  0 for arguments out of range. */
+ * under q (table, packed words, accumulators; a request with NF_WANT_TABLE
+ * holds n*n*2 more, one with NF_WANT_STRUCTURE about 9n more).  0 for
+ * arguments out of range. */
 size_t nf_fold_bytes(int n, int q);
 
+/* What a served fold keeps for its result, beside the score (flags of
+ * nf_submit): the full table (nf_poll / nf_wait / nf_poll_ex S_out), and one
+ * optimal structure as nf_fold_structure gives it (nf_poll_ex db_out), read
+ * back on the device when the fold finishes. */
+#define NF_WANT_TABLE 1
+#define NF_WANT_STRUCTURE 2
+
 /* Queue a fold (the sequence is copied).  Returns a ticket >= 0 or a negative
- * code: NF_E_INVAL/NF_E_TOOLONG for bad input, NF_E_NOMEM if the fold alone is
- * larger than the budget, NF_E_BUSY if the queue is full.  Never waits on the
- * GPU.  want_table != 0 keeps the full table for nf_poll. */
-int64_t nf_submit(const char* seq, int n, int q, int want_table);
+ * code: NF_E_INVAL/NF_E_TOOLONG for bad input or unknown flags, NF_E_NOMEM if
+ * the fold alone is larger than the budget, NF_E_BUSY if the queue is full.
+ * Never waits on the GPU.  flags: 0, or NF_WANT_TABLE and/or
+ * NF_WANT_STRUCTURE. */
+int64_t nf_submit(const char* seq, int n, int q, int flags);
 
 /* 1 = done (outputs written, ticket released), 0 = still pending, < 0 error.
  * score_out may be NULL; S_out (n*n int16) may be NULL, and is ignored unless
@@ -188,6 +197,13 @@ int nf_poll(int64_t ticket, int32_t* score_out, int16_t* S_out);
 /* Like nf_poll but blocks up to timeout_ms (< 0: no limit); NF_E_TIMEOUT when
  * the deadline passes first (the ticket stays valid). */
 int nf_wait(int64_t ticket, int timeout_ms, int32_t* score_out, int16_t* S_out);
+
+/* nf_poll and nf_wait in one, with the structure: timeout_ms = 0 polls,
+ * > 0 waits up to that long, < 0 waits without limit.  db_out (n characters,
+ * no terminator) may be NULL, and is ignored unless the ticket was submitted
+ * with NF_WANT_STRUCTURE; S_out as for nf_poll.  Same returns as nf_wait
+ * (0 only when polling). */
+int nf_poll_ex(int64_t ticket, int timeout_ms, int32_t* score_out, int16_t* S_out, char* db_out);
 
 /* Engine counters: admitted, completed, rejected requests, device steps run,
  * and the largest number of budget bytes ever held by active folds. */

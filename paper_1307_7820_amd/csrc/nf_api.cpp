@@ -389,22 +389,28 @@ size_t nf_fold_bytes(int n, int q)
     return serve_fold_bytes(n, q);
 }
 
-int64_t nf_submit(const char* seq, int n, int q, int want_table)
+int64_t nf_submit(const char* seq, int n, int q, int flags)
 {
     clear_error();
-    return serve_submit(seq, n, q, want_table);
+    return serve_submit(seq, n, q, flags);
 }
 
 int nf_poll(int64_t ticket, int32_t* score_out, int16_t* S_out)
 {
     clear_error();
-    return serve_poll(ticket, score_out, S_out, 0, false);
+    return serve_poll(ticket, score_out, S_out, nullptr, 0, false);
 }
 
 int nf_wait(int64_t ticket, int timeout_ms, int32_t* score_out, int16_t* S_out)
 {
     clear_error();
-    return serve_poll(ticket, score_out, S_out, timeout_ms, true);
+    return serve_poll(ticket, score_out, S_out, nullptr, timeout_ms, true);
+}
+
+int nf_poll_ex(int64_t ticket, int timeout_ms, int32_t* score_out, int16_t* S_out, char* db_out)
+{
+    clear_error();
+    return serve_poll(ticket, score_out, S_out, db_out, timeout_ms, timeout_ms != 0);
 }
 
 int nf_serve_stats(nf_serve_stats_t* out)

@@ -130,8 +130,8 @@ int autotune_run(int n, int qmin, int qmax, int reps);
 
 // serving engine (nf_serve.cpp)
 int serve_config(size_t budget, int max_slots, int max_queue);
-int64_t serve_submit(const char* seq, int n, int q, int want_table);
-int serve_poll(int64_t ticket, int32_t* score_out, int16_t* S_out, int timeout_ms, bool blocking);
+int64_t serve_submit(const char* seq, int n, int q, int flags);
+int serve_poll(int64_t ticket, int32_t* score_out, int16_t* S_out, char* db_out, int timeout_ms, bool blocking);
 int serve_stats(nf_serve_stats_t* out);
 void serve_shutdown();
 size_t serve_fold_bytes(int n, int q);

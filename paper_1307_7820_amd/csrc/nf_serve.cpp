@@ -22,6 +22,7 @@
 #include <thread>
 #include <unordered_map>
 #include <unordered_set>
+#include <string>
 #include <vector>
 
 #include "nf_runtime.h"
@@ -43,6 +44,7 @@ struct Request {
     std::vector<uint8_t> codes;  // padded to the fold's codes block
     int n = 0, q = 8;
     bool want_table = false;
+    bool want_structure = false;
     size_t bytes = 0;
 };
 
@@ -50,6 +52,7 @@ struct Result {
     int status = 1;  // 1 = done, < 0 = error code
     int32_t score = 0;
     std::vector<int16_t> table;
+    std::string structure;  // dot-bracket (want_structure)
 };
 
 // First-fit allocator over offsets of one device allocation.
@@ -103,9 +106,11 @@ struct Active {
     FoldDesc fd{};
     int32_t* acc = nullptr;  // 2 * NT accumulators, [diagonal parity][A]
     int16_t* S = nullptr;    // expanded table (want_table)
+    char* tb = nullptr;      // traceback area (want_structure): status, structure, spill
     int stage = 0;           // next diagonal to finish
     int slot = 0;            // index into the pinned score array
     int16_t* h_table = nullptr;
+    char* h_db = nullptr;  // pinned: traceback status (int), then the structure
 };
 
 struct StepRec {
@@ -137,10 +142,17 @@ Engine& eng()
     return e;
 }
 
-size_t serve_bytes(const Geom& g, bool want_table)
+// Traceback area of one fold: [status: kAlign][structure: n, rounded][spill]
+size_t tb_bytes(int n)
+{
+    return kAlign + (((size_t)n + kAlign - 1) & ~(kAlign - 1)) + 2 * (size_t)(n / 2 + 1) * sizeof(int2);
+}
+
+size_t serve_bytes(const Geom& g, bool want_table, bool want_structure)
 {
     size_t b = g.bytes + (size_t)2 * g.NT * kTileCells * sizeof(int32_t);
     if (want_table) b += (size_t)g.n * g.n * sizeof(int16_t) + kAlign;
+    if (want_structure) b += tb_bytes(g.n) + kAlign;
     return b;
 }
 
@@ -273,9 +285,12 @@ void admit(Engine& E, Device& D, std::vector<Active*>& active, std::vector<Activ
         a->fd.NT = g.NT;
         a->fd.ld = g.ld;
         a->acc = (int32_t*)(base + g.bytes);
-        if (a->req.want_table)
-            a->S = (int16_t*)(base + ((g.bytes + (size_t)2 * g.NT * kTileCells * sizeof(int32_t) + kAlign - 1) &
-                                      ~(kAlign - 1)));
+        size_t tail = (g.bytes + (size_t)2 * g.NT * kTileCells * sizeof(int32_t) + kAlign - 1) & ~(kAlign - 1);
+        if (a->req.want_table) {
+            a->S = (int16_t*)(base + tail);
+            tail = (tail + (size_t)g.n * g.n * sizeof(int16_t) + kAlign - 1) & ~(kAlign - 1);
+        }
+        if (a->req.want_structure) a->tb = base + tail;
         a->slot = D.free_slots.back();
         D.free_slots.pop_back();
         E.held += a->req.bytes;
@@ -297,6 +312,15 @@ void complete(Engine& E, Device& D, StepRec& rec)
             const size_t cnt = (size_t)a->req.n * a->req.n;
             res.table.assign(a->h_table, a->h_table + cnt);
             (void)hipHostFree(a->h_table);
+        }
+        if (a->req.want_structure) {
+            int status = 0;
+            std::memcpy(&status, a->h_db, sizeof status);
+            if (status != 0)
+                res.status = NF_E_DEVICE;  // the traceback found a table that is not Eq. 1's
+            else
+                res.structure.assign(a->h_db + sizeof(int), (size_t)a->req.n);
+            (void)hipHostFree(a->h_db);
         }
         out.push_back({a->req.ticket, std::move(res)});
     }
@@ -515,6 +539,25 @@ void engine_main()
                 } else if (ok && a->req.want_table) {
                     ok = hipHostMalloc((void**)&a->h_table, 16, hipHostMallocDefault) == hipSuccess;
                 }
+                if (ok && a->req.want_structure) {
+                    // one optimal structure, read back on the device before the
+                    // fold's memory is released
+                    const int n = a->req.n;
+                    ok = hipHostMalloc((void**)&a->h_db, sizeof(int) + (size_t)n + 16, hipHostMallocDefault) ==
+                         hipSuccess;
+                    if (ok && n > 0) {
+                        char* db = a->tb + kAlign;
+                        int2* spill = (int2*)(db + (((size_t)n + kAlign - 1) & ~(kAlign - 1)));
+                        ok = launch_traceback(a->fd.F, a->g.ld, a->fd.codes, n, spill, n / 2 + 1, db, (int*)a->tb,
+                                              D.s1) == hipSuccess;
+                        ok = ok && hipMemcpyAsync(a->h_db, a->tb, sizeof(int), hipMemcpyDeviceToHost, D.s1) ==
+                                       hipSuccess;
+                        ok = ok && hipMemcpyAsync(a->h_db + sizeof(int), db, (size_t)n, hipMemcpyDeviceToHost,
+                                                  D.s1) == hipSuccess;
+                    } else if (ok) {
+                        std::memset(a->h_db, 0, sizeof(int));
+                    }
+                }
             }
         }
         // the step is complete when both streams are through it
@@ -564,6 +607,7 @@ void engine_main()
     fail_all(E, active, code);
     for (auto* a : active) {
         if (a->h_table) (void)hipHostFree(a->h_table);
+        if (a->h_db) (void)hipHostFree(a->h_db);
         delete a;
     }
     engine_release(D);
@@ -587,9 +631,9 @@ int serve_config(size_t budget, int max_slots, int max_queue)
     return NF_OK;
 }
 
-size_t serve_fold_bytes(int n, int q) { return serve_bytes(make_geom(n, q), false); }
+size_t serve_fold_bytes(int n, int q) { return serve_bytes(make_geom(n, q), false, false); }
 
-int64_t serve_submit(const char* seq, int n, int q, int want_table)
+int64_t serve_submit(const char* seq, int n, int q, int flags)
 {
     int rc = check_length(n);
     if (rc) return rc;
@@ -605,8 +649,10 @@ int64_t serve_submit(const char* seq, int n, int q, int want_table)
     if ((rc = encode_sequence(seq, n, r.codes.data()))) return rc;
     r.n = n;
     r.q = q;
-    r.want_table = want_table != 0;
-    r.bytes = serve_bytes(g, r.want_table);
+    if (flags & ~(NF_WANT_TABLE | NF_WANT_STRUCTURE)) return fail(NF_E_INVAL, "unknown flags 0x%x", flags);
+    r.want_table = (flags & NF_WANT_TABLE) != 0;
+    r.want_structure = (flags & NF_WANT_STRUCTURE) != 0;
+    r.bytes = serve_bytes(g, r.want_table, r.want_structure);
     Engine& E = eng();
     std::unique_lock<std::mutex> lk(E.mu);
     if (!E.running) {
@@ -653,7 +699,7 @@ int64_t serve_submit(const char* seq, int n, int q, int want_table)
     return t;
 }
 
-int serve_poll(int64_t ticket, int32_t* score_out, int16_t* S_out, int timeout_ms, bool blocking)
+int serve_poll(int64_t ticket, int32_t* score_out, int16_t* S_out, char* db_out, int timeout_ms, bool blocking)
 {
     Engine& E = eng();
     std::unique_lock<std::mutex> lk(E.mu);
@@ -666,6 +712,7 @@ int serve_poll(int64_t ticket, int32_t* score_out, int16_t* S_out, int timeout_m
             if (res.status < 0) return fail(res.status, "ticket %lld did not complete", (long long)ticket);
             if (score_out) *score_out = res.score;
             if (S_out && !res.table.empty()) std::memcpy(S_out, res.table.data(), res.table.size() * sizeof(int16_t));
+            if (db_out && !res.structure.empty()) std::memcpy(db_out, res.structure.data(), res.structure.size());
             return 1;
         }
         if (!E.live.count(ticket)) return fail(NF_E_NOTFOUND, "unknown or released ticket %lld", (long long)ticket);

@@ -27,6 +27,8 @@ NF_E_TOOLONG = -6
 NF_E_TIMEOUT = -7
 NF_E_ABORTED = -8
 NF_MAX_N = 65534
+NF_WANT_TABLE = 1
+NF_WANT_STRUCTURE = 2
 
 _CODE_NAMES = {
     NF_E_INVAL: "NF_E_INVAL", NF_E_NOMEM: "NF_E_NOMEM", NF_E_DEVICE: "NF_E_DEVICE",
@@ -39,7 +41,7 @@ EXPORTS = [
     "nf_last_error", "nf_init", "nf_shutdown", "nf_precompute_R", "nf_copy_R", "nf_fold", "nf_fold_structure",
     "nf_fold_dev", "nf_batch_create", "nf_batch_run", "nf_batch_scores", "nf_batch_table",
     "nf_batch_info", "nf_batch_structures", "nf_batch_destroy", "nf_fold_batch", "nf_serve_config", "nf_fold_bytes",
-    "nf_submit", "nf_poll", "nf_wait", "nf_serve_stats", "nf_autotune_q", "nf_autotune",
+    "nf_submit", "nf_poll", "nf_wait", "nf_poll_ex", "nf_serve_stats", "nf_autotune_q", "nf_autotune",
     "nf_profile_fold",
 ]
 
@@ -107,6 +109,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "nf_submit": (c_i64, [ctypes.c_char_p, c_int, c_int, c_int]),
         "nf_poll": (c_int, [c_i64, vp, vp]),
         "nf_wait": (c_int, [c_i64, c_int, vp, vp]),
+        "nf_poll_ex": (c_int, [c_i64, c_int, vp, vp, vp]),
         "nf_serve_stats": (c_int, [ctypes.POINTER(ServeStats)]),
         "nf_autotune_q": (c_int, [c_int]),
         "nf_autotune": (c_int, [c_int, c_int, c_int, c_int]),
@@ -282,9 +285,10 @@ def nf_fold_bytes(n: int, q: int = 0) -> int:
     return int(load().nf_fold_bytes(n, q))
 
 
-def nf_submit(seq: str, q: int = 0, want_table: bool = False) -> int:
+def nf_submit(seq: str, q: int = 0, want_table: bool = False, want_structure: bool = False) -> int:
     b = seq.encode("ascii")
-    return _check(load().nf_submit(b, len(b), q, 1 if want_table else 0))
+    flags = (NF_WANT_TABLE if want_table else 0) | (NF_WANT_STRUCTURE if want_structure else 0)
+    return _check(load().nf_submit(b, len(b), q, flags))
 
 
 def nf_poll(ticket: int, n: int = 0, want_table: bool = False):
@@ -300,6 +304,20 @@ def nf_wait(ticket: int, timeout_ms: int = -1, n: int = 0, want_table: bool = Fa
     S = np.zeros((n, n), dtype=np.int16) if want_table else None
     _check(load().nf_wait(ticket, timeout_ms, ctypes.addressof(score), _ptr(S) if (S is not None and n) else None))
     return (score.value, S) if want_table else score.value
+
+
+def nf_poll_ex(ticket: int, timeout_ms: int = -1, n: int = 0, want_table: bool = False,
+               want_structure: bool = False):
+    """(done, score, table, structure); timeout_ms 0 polls, < 0 waits without limit."""
+    score = ctypes.c_int32(-1)
+    S = np.zeros((n, n), dtype=np.int16) if want_table else None
+    db = ctypes.create_string_buffer(max(1, n)) if want_structure else None
+    rc = _check(load().nf_poll_ex(ticket, timeout_ms, ctypes.addressof(score),
+                                  _ptr(S) if (S is not None and n) else None,
+                                  ctypes.addressof(db) if db is not None else None))
+    if rc != 1:
+        return (False, None, None, None)
+    return (True, score.value, S, db.raw[:n].decode("ascii") if db is not None else None)
 
 
 def nf_serve_stats() -> ServeStats:

@@ -128,3 +128,34 @@ def test_shutdown_aborts_or_completes(nf):
             assert done and score == oracle.fold_score(s)
         except nf.NFError as err:
             assert err.code in (nf.NF_E_ABORTED, nf.NF_E_NOTFOUND)
+
+
+def test_structures_in_a_mix(nf):
+    # NF_WANT_STRUCTURE: the engine traces each fold back on the device when it
+    # finishes; the structure equals the oracle's and the single-fold path's,
+    # with and without the table, while other folds are in flight
+    from pins import check_structure
+    nf.nf_serve_config(0, 32, 0)
+    trace = gen.serving_trace(40, 0.0, seed=(204, 0), short=(50, 400), long=(1200, 2600), p_short=0.75)
+    seqs = [s for _, s in trace] + ["", "A", "GGGAAACCC"]
+    sub = []
+    for k, s in enumerate(seqs):
+        wt, ws = (k % 3 == 0), (k % 3 != 2)
+        sub.append((nf.nf_submit(s, q=8, want_table=wt, want_structure=ws), s, wt, ws))
+    for t, s, wt, ws in sub:
+        done, score, S, db = nf.nf_poll_ex(t, 120000, len(s), wt, ws)
+        assert done and score == oracle.fold_score(s), len(s)
+        if wt:
+            assert np.array_equal(S, oracle.fold_table(s)), len(s)
+        if ws:
+            assert db == oracle.structure(s), len(s)
+            check_structure(s, db, score)
+            if s:
+                assert db == nf.nf_fold_structure(s, q=8)[1], len(s)
+        else:
+            assert db is None
+    with pytest.raises(nf.NFError) as e:
+        load = nf.load()
+        rc = load.nf_submit(b"ACGU", 4, 8, 4)  # unknown flag
+        nf._check(rc)
+    assert e.value.code == nf.NF_E_INVAL
