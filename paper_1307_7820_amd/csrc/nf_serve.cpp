@@ -172,7 +172,9 @@ struct Device {
     DevBuf arena_mem;
     Arena arena;
     hipStream_t s1 = nullptr, s2 = nullptr;
+    hipStream_t s3 = nullptr;  // tracebacks of finished folds, beside the steps
     hipEvent_t ev_tile = nullptr, ev_btw = nullptr;
+    hipEvent_t ev_fin = nullptr, ev_end = nullptr;
     const uint8_t* R[NF_Q_MAX + 1] = {nullptr};
     // ring of item buffers (pinned staging + device copy)
     struct Ring {
@@ -213,6 +215,9 @@ int engine_init(Engine& E, Device& D)
     HIPCHK(hipStreamCreateWithFlags(&D.s2, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&D.ev_tile, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&D.ev_btw, hipEventDisableTiming));
+    HIPCHK(hipStreamCreateWithFlags(&D.s3, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&D.ev_fin, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&D.ev_end, hipEventDisableTiming));
     int rc = D.arena_mem.alloc(E.budget);
     if (rc) return rc;
     D.arena.reset(E.budget);
@@ -227,6 +232,7 @@ void engine_release(Device& D)
 {
     if (D.s1) (void)hipStreamSynchronize(D.s1);
     if (D.s2) (void)hipStreamSynchronize(D.s2);
+    if (D.s3) (void)hipStreamSynchronize(D.s3);
     for (auto& r : D.ring) {
         if (r.host) (void)hipHostFree(r.host);
         if (r.free_ev) (void)hipEventDestroy(r.free_ev);
@@ -239,6 +245,9 @@ void engine_release(Device& D)
     if (D.ev_btw) (void)hipEventDestroy(D.ev_btw);
     if (D.s1) (void)hipStreamDestroy(D.s1);
     if (D.s2) (void)hipStreamDestroy(D.s2);
+    if (D.ev_fin) (void)hipEventDestroy(D.ev_fin);
+    if (D.ev_end) (void)hipEventDestroy(D.ev_end);
+    if (D.s3) (void)hipStreamDestroy(D.s3);
 }
 
 int ensure_ring(Device::Ring& r, size_t bytes)
@@ -522,7 +531,10 @@ void engine_main()
         ok = ok && hipStreamWaitEvent(D.s2, D.ev_tile, 0) == hipSuccess;
         launch_groups(d_btw, wbtw, 2, D.s2);
         ok = ok && hipEventRecord(D.ev_btw, D.s2) == hipSuccess;
-        // finished folds: score (and table) to pinned memory
+        // finished folds: score (and table) to pinned memory; structures are
+        // traced back on s3 once this step's finishes are done, so the next
+        // steps on s1 do not wait for them
+        bool any_tb = false;
         if (ok && !rec.finishing.empty()) {
             ok = launch_scores(d_fin, (int)wfin.size(), (int32_t*)D.d_scores.p, D.s1) == hipSuccess;
             for (size_t k = 0; ok && k < rec.finishing.size(); ++k) {
@@ -546,14 +558,19 @@ void engine_main()
                     ok = hipHostMalloc((void**)&a->h_db, sizeof(int) + (size_t)n + 16, hipHostMallocDefault) ==
                          hipSuccess;
                     if (ok && n > 0) {
+                        if (!any_tb) {
+                            ok = hipEventRecord(D.ev_fin, D.s1) == hipSuccess &&
+                                 hipStreamWaitEvent(D.s3, D.ev_fin, 0) == hipSuccess;
+                            any_tb = true;
+                        }
                         char* db = a->tb + kAlign;
                         int2* spill = (int2*)(db + (((size_t)n + kAlign - 1) & ~(kAlign - 1)));
-                        ok = launch_traceback(a->fd.F, a->g.ld, a->fd.codes, n, spill, n / 2 + 1, db, (int*)a->tb,
-                                              D.s1) == hipSuccess;
-                        ok = ok && hipMemcpyAsync(a->h_db, a->tb, sizeof(int), hipMemcpyDeviceToHost, D.s1) ==
+                        ok = ok && launch_traceback(a->fd.F, a->g.ld, a->fd.codes, n, spill, n / 2 + 1, db,
+                                                    (int*)a->tb, D.s3) == hipSuccess;
+                        ok = ok && hipMemcpyAsync(a->h_db, a->tb, sizeof(int), hipMemcpyDeviceToHost, D.s3) ==
                                        hipSuccess;
                         ok = ok && hipMemcpyAsync(a->h_db + sizeof(int), db, (size_t)n, hipMemcpyDeviceToHost,
-                                                  D.s1) == hipSuccess;
+                                                  D.s3) == hipSuccess;
                     } else if (ok) {
                         std::memset(a->h_db, 0, sizeof(int));
                     }
@@ -563,7 +580,13 @@ void engine_main()
         // the step is complete when both streams are through it
         ok = ok && hipStreamWaitEvent(D.s1, D.ev_btw, 0) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&rec.ev, hipEventDisableTiming) == hipSuccess;
-        ok = ok && hipEventRecord(rec.ev, D.s1) == hipSuccess;
+        if (any_tb) {  // ... and the tracebacks on s3
+            ok = ok && hipEventRecord(D.ev_end, D.s1) == hipSuccess;
+            ok = ok && hipStreamWaitEvent(D.s3, D.ev_end, 0) == hipSuccess;
+            ok = ok && hipEventRecord(rec.ev, D.s3) == hipSuccess;
+        } else {
+            ok = ok && hipEventRecord(rec.ev, D.s1) == hipSuccess;
+        }
         ok = ok && hipEventRecord(rg.free_ev, D.s1) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
