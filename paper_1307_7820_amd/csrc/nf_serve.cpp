@@ -120,6 +120,9 @@ struct StepRec {
 };
 
 struct Engine {
+    // `life` orders submit, config and shutdown against one another: it is
+    // the outermost lock, and the engine thread never takes it.
+    std::mutex life;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     size_t budget = 0;
@@ -189,9 +192,16 @@ struct Device {
     std::vector<int> free_slots;
 };
 
+// The engine thread is ending: fail what it holds and mark it stopped in the
+// same critical section, so that a later submit starts a new thread rather
+// than queueing behind one that will never serve it.  The thread takes no
+// lock after this, so a submit may join it while holding E.mu.
 void fail_all(Engine& E, std::vector<Active*>& active, int code)
 {
     std::lock_guard<std::mutex> lk(E.mu);
+    E.running = false;
+    E.held = 0;  // the thread's arena goes with it
+    E.head_bypassed = 0;
     for (auto* a : active) {
         E.done[a->req.ticket] = Result{code, 0, {}};
         E.live.erase(a->req.ticket);
@@ -643,6 +653,7 @@ void engine_main()
 int serve_config(size_t budget, int max_slots, int max_queue)
 {
     Engine& E = eng();
+    std::lock_guard<std::mutex> life(E.life);
     std::lock_guard<std::mutex> lk(E.mu);
     if (E.running) return fail(NF_E_BUSY, "serving engine already running; call nf_shutdown first");
     if (max_slots < 0 || max_queue < 0) return fail(NF_E_INVAL, "negative limits");
@@ -677,6 +688,7 @@ int64_t serve_submit(const char* seq, int n, int q, int flags)
     r.want_structure = (flags & NF_WANT_STRUCTURE) != 0;
     r.bytes = serve_bytes(g, r.want_table, r.want_structure);
     Engine& E = eng();
+    std::lock_guard<std::mutex> life(E.life);
     std::unique_lock<std::mutex> lk(E.mu);
     if (!E.running) {
         if (!E.configured) {
@@ -707,7 +719,7 @@ int64_t serve_submit(const char* seq, int n, int q, int flags)
         return fail(NF_E_BUSY, "serving queue full (%d requests)", E.max_queue);
     }
     if (!E.running) {
-        if (E.th.joinable()) E.th.join();
+        if (E.th.joinable()) E.th.join();  // a thread that has ended: it no longer takes E.mu
         E.stop = false;
         E.running = true;
         E.st.budget_bytes = E.budget;
@@ -762,6 +774,7 @@ int serve_stats(nf_serve_stats_t* out)
 void serve_shutdown()
 {
     Engine& E = eng();
+    std::lock_guard<std::mutex> life(E.life);
     {
         std::lock_guard<std::mutex> lk(E.mu);
         if (!E.running && !E.th.joinable()) return;

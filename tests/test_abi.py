@@ -96,3 +96,72 @@ def test_schedule_hook_rejects_bad_input(lib):
     arr = (ctypes.c_int * 2)(3, 0)
     assert lib.nf_test_schedule(arr, 2, 1024, None, 0) == nf.NF_E_INVAL
     assert lib.nf_test_schedule(arr, 1, 0, None, 0) == nf.NF_E_INVAL
+
+
+def test_serving_engine_that_failed_does_not_strand_later_requests(lib):
+    # Without a device the engine thread's set-up fails: the request it holds
+    # completes with NF_E_DEVICE, and a request submitted after the thread has
+    # ended starts a new one (which fails the same way) instead of waiting in
+    # a queue that nothing serves.
+    from paper_1307_7820_amd import nf
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("checks the failure path of a machine without a GPU")
+    nf.nf_shutdown()
+    try:
+        nf.nf_serve_config(1 << 26)
+        for _ in range(2):
+            t = nf.nf_submit("GGGAAACCC")
+            with pytest.raises(nf.NFError) as e:
+                nf.nf_wait(t, timeout_ms=10000)
+            assert e.value.code == nf.NF_E_DEVICE, str(e.value)
+    finally:
+        nf.nf_shutdown()
+
+
+def test_serving_submit_and_shutdown_race(lib):
+    # Submits from several threads while another shuts the engine down again
+    # and again: every ticket handed out resolves (here, without a device, to
+    # an error) and none waits forever.
+    import threading
+    from paper_1307_7820_amd import nf
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("checks the failure path of a machine without a GPU")
+    nf.nf_shutdown()
+    nf.nf_serve_config(1 << 26)
+    tickets, lock, stop = [], threading.Lock(), threading.Event()
+
+    def submitter():
+        while not stop.is_set():
+            try:
+                t = nf.nf_submit("GGGAAACCC")
+            except nf.NFError:
+                continue  # refused at submit: nothing to resolve
+            with lock:
+                tickets.append(t)
+
+    def stopper():
+        for _ in range(50):
+            nf.nf_shutdown()
+            try:
+                nf.nf_serve_config(1 << 26)
+            except nf.NFError:
+                pass  # a submit restarted the engine first
+
+    try:
+        ts = [threading.Thread(target=submitter) for _ in range(3)]
+        for t in ts:
+            t.start()
+        stopper()
+        stop.set()
+        for t in ts:
+            t.join(30)
+        assert tickets
+        for t in tickets:
+            with pytest.raises(nf.NFError) as e:
+                nf.nf_wait(t, timeout_ms=10000)
+            assert e.value.code in (nf.NF_E_DEVICE, nf.NF_E_ABORTED), str(e.value)
+    finally:
+        stop.set()
+        nf.nf_shutdown()
