@@ -12,6 +12,7 @@ using namespace nf;
 
 namespace {
 std::recursive_mutex g_api;
+
 }
 
 struct nf_batch {
@@ -86,8 +87,9 @@ int nf_copy_R(int q, uint8_t* out, size_t cap)
 
 // Encode seq, fill its table on the library stream and leave the plan in *out
 // (the copies and the fill are enqueued, not waited for; `padded` must live
-// until the stream is synchronised).
-static int fill_single(const char* seq, int n, int q, Plan** out, std::vector<uint8_t>& padded)
+// until the stream is synchronised, which `fence`, armed here once the device
+// is up, sees to on every return).
+static int fill_single(const char* seq, int n, int q, Plan** out, std::vector<uint8_t>& padded, StreamFence& fence)
 {
     int rc = check_length(n);
     if (rc) return rc;
@@ -96,6 +98,7 @@ static int fill_single(const char* seq, int n, int q, Plan** out, std::vector<ui
     std::vector<uint8_t> codes(n);
     if ((rc = encode_sequence(seq, n, codes.data()))) return rc;
     if ((rc = ensure_device())) return rc;
+    fence.s = ctx().stream;
     q = resolve_q(q, n);
     Plan* p = nullptr;
     if ((rc = single_plan(n, q, &p))) return rc;
@@ -115,11 +118,12 @@ int nf_fold(const char* seq, int n, int q, int16_t* S_out)
     clear_error();
     Plan* p = nullptr;
     std::vector<uint8_t> padded;
-    int rc = fill_single(seq, n, q, &p, padded);
+    int32_t score = 0;
+    StreamFence fence;
+    int rc = fill_single(seq, n, q, &p, padded, fence);
     if (rc) return rc;
     const Geom& g = p->geom[0];
     hipStream_t s = ctx().stream;
-    int32_t score = 0;
     HIPCHK(hipMemcpyAsync(&score, p->d_scores.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (S_out && n > 0) {
         const size_t bytes = (size_t)n * n * sizeof(int16_t);
@@ -138,14 +142,15 @@ int nf_fold_structure(const char* seq, int n, int q, char* db_out)
     if (!db_out && n > 0) return fail(NF_E_INVAL, "db_out is NULL");
     Plan* p = nullptr;
     std::vector<uint8_t> padded;
-    int rc = fill_single(seq, n, q, &p, padded);
+    int32_t score = 0;
+    int32_t status = 0;
+    std::vector<char> db(n);
+    StreamFence fence;
+    int rc = fill_single(seq, n, q, &p, padded, fence);
     if (rc) return rc;
     const Geom& g = p->geom[0];
     hipStream_t s = ctx().stream;
-    int32_t score = 0;
-    int32_t status = 0;
     HIPCHK(hipMemcpyAsync(&score, p->d_scores.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    std::vector<char> db(n);
     if (n > 0) {
         // [status: 256 B][structure: n B, rounded up to 256][spill: 2 (n/2 + 1) int2]
         const int cap = n / 2 + 1;
@@ -215,6 +220,7 @@ int nf_batch_create(const char* const* seqs, const int* ns, int count, int q, nf
     Plan& p = *b->plan;
     // zero-padded codes of every fold; the host buffers live until the copies finish
     hipStream_t s = ctx().stream;
+    StreamFence fence{s};
     for (int i = 0; i < count; ++i) {
         codes[i].resize(p.geom[i].codes_bytes, 0);
         HIPCHK(hipMemcpyAsync((void*)p.h_folds[i].codes, codes[i].data(), codes[i].size(), hipMemcpyHostToDevice, s));
@@ -266,6 +272,7 @@ int nf_batch_table(nf_batch* b, int idx, int16_t* S_out)
     int rc;
     if (p.d_S.bytes < bytes && (rc = p.d_S.alloc(bytes))) return rc;
     hipStream_t s = ctx().stream;
+    StreamFence fence{s};
     HIPCHK(launch_expand(p.h_folds[idx].F, p.geom[idx].ld, n, (int16_t*)p.d_S.p, s));
     HIPCHK(hipMemcpyAsync(S_out, p.d_S.p, bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -319,6 +326,7 @@ int nf_batch_structures(nf_batch* b, char* const* db_outs)
     hipStream_t s = ctx().stream;
     std::vector<int> status(nw, 0);
     std::vector<char> db(db_total);
+    StreamFence fence{s};
     HIPCHK(hipMemcpyAsync(base, work.data(), nw * sizeof(TracebackWork), hipMemcpyHostToDevice, s));
     HIPCHK(launch_traceback_many((const TracebackWork*)base, (int)nw, s));
     HIPCHK(hipMemcpyAsync(status.data(), base + st_off, nw * sizeof(int), hipMemcpyDeviceToHost, s));

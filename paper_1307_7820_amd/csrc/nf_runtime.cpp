@@ -386,6 +386,7 @@ int plan_allocate(Plan& p)
     if ((rc = p.d_btw.alloc(std::max<size_t>(1, wb.size()) * sizeof(BetweenWork)))) return rc;
     if ((rc = p.d_scores.alloc(std::max<size_t>(1, fd.size()) * sizeof(int32_t)))) return rc;
     hipStream_t s = ctx().stream;
+    StreamFence fence{s};  // fd, wd, wt and wb are read by the copies below
     // accumulators start at zero (max with 0 is neutral: every score is >= 0)
     HIPCHK(hipMemsetAsync(p.d_part.p, 0, p.d_part.bytes, s));
     HIPCHK(hipMemcpyAsync(p.d_folds.p, fd.data(), fd.size() * sizeof(FoldDesc), hipMemcpyHostToDevice, s));
@@ -724,6 +725,7 @@ int autotune_run(int n, int qmin, int qmax, int reps)
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    StreamFence fence{c.stream};  // the uploads read `codes`
     for (int q = qmin; q <= qmax; ++q) {
         Plan* p = nullptr;
         if ((rc = single_plan(n, q, &p))) break;

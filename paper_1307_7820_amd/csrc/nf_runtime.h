@@ -26,6 +26,18 @@ void clear_error();
         }                                                                                         \
     } while (0)
 
+// Waits for a stream when a function returns, so that no copy still in
+// flight on an early error return reads or writes host memory of the
+// caller's or of the returning frame.  Declare it after the host buffers it
+// guards, so it runs before they are freed; a null stream is not waited on.
+struct StreamFence {
+    hipStream_t s = nullptr;
+    ~StreamFence()
+    {
+        if (s) (void)hipStreamSynchronize(s);
+    }
+};
+
 // Owned device allocation.
 struct DevBuf {
     void* p = nullptr;
