@@ -11,6 +11,9 @@ torch.cuda.synchronize() and HIP events.
 GCUPS = n(n+1)/2 table cells / fill time / 1e9 (R is built once, before the
 timed region; no host transfers inside it).
 
+Unless --q is given, q (4..8) and then the between-group chunks per step are
+chosen first by nf_autotune, outside the timed region; config records both.
+
 Printed beside the headline (one JSON line on stdout; progress on stderr):
   roofline      dominant kernel (by time) measured with per-launch HIP events
   cpu_baseline  the CPU oracle timed on this host on the same sequence
@@ -33,6 +36,7 @@ if ROOT not in sys.path:
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: int32 VALU lane-ops/s
 OPS_PER_LOOKUP = 2.5                          # index add + 3-input add + half a 3-input max
 OPS_PER_TERM = 2.0                            # add + max of one Eq. 1 term
+TUNE_REPS = 5                                 # folds per candidate when the headline q and chunk target are tuned
 PEAK_HBM = 8.0e12
 
 
@@ -81,13 +85,15 @@ def kernels_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_bytes(kernel: str, q: int, n: int):
+def traffic_bytes(kernel: str, q: int, n: int, target: int):
     """HBM bytes per launch of `kernel`, from the committed rocprofv3 counter
     summary profiles/<kernel>_q<q>_<workload>_pmc.txt: FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch, separate runs), each scaled by what the same
     counter reads for a plain device copy of known size.  None when there is
-    no summary for this kernel and workload, or when the kernel source has
-    changed since the counters were taken (its hash is in the summary)."""
+    no summary for this kernel and workload, when the kernel source has
+    changed since the counters were taken (its hash is in the summary), or
+    when the counters were taken at another number of between-group chunks
+    per step than `target`."""
     wl = WORKLOAD_NAMES.get(n)
     if wl is None:
         return None
@@ -104,6 +110,8 @@ def traffic_bytes(kernel: str, q: int, n: int):
     try:
         if vals.get("kernels_sha256") != kernels_source_hash():
             return None
+        if int(vals.get("target", "0")) != target:
+            return None
         return 1024.0 * (float(vals["fetch_kib"]) * float(vals["fetch_scale"]) +
                          float(vals["write_kib"]) * float(vals["write_scale"]))
     except (KeyError, ValueError):
@@ -118,6 +126,7 @@ def roofline(nf, codes, n, q, reps=3):
     from the work lists; duration = the kernel's own start and end, recorded
     into HIP events by its dispatch on the launching stream."""
     prof = nf.nf_profile_fold(codes, n, q, reps)
+    target = nf.nf_autotune_target(n)  # the chunks per step the profiled plan was built with
     ks = [i for i in range(len(nf.KERNEL_NAMES)) if prof.launches[i] > 0]
     k = max(ks, key=lambda i: prof.ms[i])
     name = nf.KERNEL_NAMES[k]
@@ -132,8 +141,8 @@ def roofline(nf, codes, n, q, reps=3):
            "lookups_per_launch": prof.lookups[k] / prof.launches[k],
            "terms_per_launch": prof.splits[k] / prof.launches[k],
            "glookups_per_s": prof.lookups[k] / (prof.ms[k] / 1e3) / 1e9,
-           "traffic": traffic_bytes(name, q, n),
-           "q": prof.q, "tile": prof.tile}
+           "traffic": traffic_bytes(name, q, n, target),
+           "q": prof.q, "tile": prof.tile, "between_chunks_per_step": target}
     return out
 
 
@@ -423,7 +432,8 @@ def run_only(args, torch, gen, nf):
         seq = gen.workload_n6000() if args.only == "n6000" else gen.workload_n16000()
     q = args.q if args.q else 8
     ms, wall, score, _ = time_fold(nf, torch, seq, q, args.steps, args.warmup)
-    print(json.dumps({"only": args.only, "n": len(seq), "q": q, "ms_per_fold": ms / args.steps,
+    print(json.dumps({"only": args.only, "n": len(seq), "q": q,
+                      "between_chunks_per_step": nf.nf_autotune_target(len(seq)), "ms_per_fold": ms / args.steps,
                       "gcups": cells(len(seq)) * args.steps / (ms / 1e3) / 1e9, "score": score}))
 
 
@@ -454,8 +464,16 @@ def main():
     nf.nf_init(0)
     seq = gen.workload_n6000()
     n = len(seq)
-    q = args.q if args.q else nf.nf_autotune_q(n)
-    log("bench: n=%d q=%d warmup=%d steps=%d" % (n, q, args.warmup, args.steps))
+    if args.q:
+        q = args.q
+    else:
+        # q in 4..8, then the chunk target at that q, by timing (not timed here)
+        t0 = time.perf_counter()
+        q = nf.nf_autotune(n, 4, 8, TUNE_REPS)
+        log("bench: autotune n=%d: q=%d, chunk target %d (%.2f s)"
+            % (n, q, nf.nf_autotune_target(n), time.perf_counter() - t0))
+    target = nf.nf_autotune_target(n)
+    log("bench: n=%d q=%d target=%d warmup=%d steps=%d" % (n, q, target, args.warmup, args.steps))
     ms, wall, score, codes = time_fold(nf, torch, seq, q, args.steps, args.warmup)
     ms_per = ms / args.steps
     value = cells(n) * args.steps / (ms / 1e3) / 1e9
@@ -506,7 +524,8 @@ def main():
         "split_equivalent_gsps": splits(n) / (ms_per / 1e3) / 1e9,
         "dtype": "int16", "data": "synthetic",
         "config": {"workload": "single iid uniform ACGU sequence, n=6000, two-vector Four-Russians fill",
-                   "n": n, "q": q, "tile": roof.get("tile"), "score": score},
+                   "n": n, "q": q, "between_chunks_per_step": target, "autotuned": not args.q,
+                   "tile": roof.get("tile"), "score": score},
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": roof,
         "cpu_baseline": cpu,

@@ -215,13 +215,25 @@ typedef struct {
 int nf_serve_stats(nf_serve_stats_t* out);
 
 /* ---- Tuning ----
- * q and launch shape chosen for sequences of length n (what q = 0 resolves
- * to).  The choice comes from the autotune cache file named by
- * NF_AUTOTUNE_CACHE if set and readable, else from built-in defaults. */
+ * Choices are kept per length bucket (n < 256, < 512, ..., >= 65536).  They
+ * come from the autotune cache file named by NF_AUTOTUNE_CACHE if set and
+ * readable (one line per bucket: "bucket q target"; a line without the
+ * target leaves it at its default), from nf_autotune, else from built-in
+ * defaults.  Neither changes a result: every q and every target fills the
+ * same table.
+ *
+ * The q that q = 0 resolves to for sequences of length n (group width of
+ * Eq. 3; default 8). */
 int nf_autotune_q(int n);
-/* Time the fill for q in qmin..qmax at length n (reps folds each) and record
- * the fastest in the in-memory cache (and in the cache file if set).  Returns
- * the chosen q. */
+/* The launch shape of a single fold of length n: the number of between-group
+ * chunks (workgroups) each wavefront step is cut into (default 1024; the
+ * environment variable NF_BETWEEN_TARGET, if set, overrides it and every
+ * tuned value).  Batches use the default.  NF_E_INVAL for n out of range. */
+int nf_autotune_target(int n);
+/* Time the fill at length n (reps folds each, after one warm-up fold): first
+ * q in qmin..qmax at the default target, then the targets 1024, 256, 512 and
+ * 2048 at the fastest q.  Records both in the in-memory cache (and in the
+ * cache file if set).  Returns the chosen q. */
 int nf_autotune(int n, int qmin, int qmax, int reps);
 
 /* ---- Diagnostics ----

@@ -162,13 +162,23 @@ Geom make_geom(int n, int q)
     return g;
 }
 
-// Between chunks per wavefront step (NF_BETWEEN_TARGET overrides): enough
-// workgroups to fill the device.
-int between_target(int /*mode*/)
+static int bucket_of(int n);
+static void load_tune_file();
+
+// Between chunks per wavefront step: NF_BETWEEN_TARGET if set; else, for a
+// single fold (n_single >= 0), the autotuned value of its length bucket; else
+// enough workgroups to fill the device.
+int between_target(int n_single)
 {
     const char* e = getenv("NF_BETWEEN_TARGET");
     const int env = e ? atoi(e) : 0;
-    return env > 0 ? env : 1024;
+    if (env > 0) return env;
+    if (n_single >= 0) {
+        load_tune_file();
+        const int t = ctx().tuned_target[bucket_of(n_single)];
+        if (t > 0) return t;
+    }
+    return kDefaultTarget;
 }
 
 // Append the between-group items of diagonal dd for the listed folds.  The
@@ -597,7 +607,8 @@ int plan_enqueue(Plan& p, hipStream_t s)
     return NF_OK;
 }
 
-int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out)
+// target > 0 fixes the between chunks per step; 0 takes between_target's.
+int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out, int target)
 {
     auto p = std::make_unique<Plan>();
     p->q = q;
@@ -609,23 +620,26 @@ int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out)
     p->mode = plan_mode_for(NTs);
     p->plain = plain_between_for(q);
     if (p->plain) p->mode = kModeStaged;  // the fused step has the lookup built in
-    build_schedule(NTs, between_target(p->mode), p->sc);
+    p->target = target > 0 ? target : between_target(ns.size() == 1 ? ns[0] : -1);
+    build_schedule(NTs, p->target, p->sc);
     int rc = plan_allocate(*p);
     if (rc) return rc;
     out = std::move(p);
     return NF_OK;
 }
 
-// Single-fold plans are cached by (n, q), least recently used first out.
-int single_plan(int n, int q, Plan** out)
+// Single-fold plans are cached by (n, q) and the chunk target, least recently
+// used first out.
+int single_plan(int n, int q, Plan** out, int target)
 {
     Context& c = ctx();
+    if (target <= 0) target = between_target(n);
     // NF_MODE and NF_BETWEEN are read when a plan is made, so they are part of the key
     const char* me = getenv("NF_MODE");
     const int mode_env = !me ? 0 : strcmp(me, "fused") == 0 ? 1 : strcmp(me, "staged") == 0 ? 2 : 0;
     const long long key = (((long long)n * 16 + q) * 2 + (plain_between_for(q) ? 1 : 0)) * 3 + mode_env;
     for (auto it = c.plans.begin(); it != c.plans.end(); ++it) {
-        if (it->first == key) {
+        if (it->first == key && it->second->target == target) {
             auto ent = std::move(*it);
             c.plans.erase(it);
             c.plans.push_back(std::move(ent));
@@ -643,10 +657,10 @@ int single_plan(int n, int q, Plan** out)
         c.plans.erase(c.plans.begin());
     }
     std::unique_ptr<Plan> p;
-    int rc = make_plan({n}, q, p);
+    int rc = make_plan({n}, q, p, target);
     if (rc == NF_E_NOMEM && !c.plans.empty()) {  // drop every cached plan and retry once
         c.plans.clear();
-        rc = make_plan({n}, q, p);
+        rc = make_plan({n}, q, p, target);
     }
     if (rc) return rc;
     c.plans.push_back({key, std::move(p)});
@@ -682,10 +696,16 @@ static void load_tune_file()
     c.tune_loaded = true;
     const char* path = getenv("NF_AUTOTUNE_CACHE");
     if (!path) return;
+    // one line per length bucket: "bucket q [target]"
     std::ifstream in(path);
-    int b, q;
-    while (in >> b >> q)
-        if (b >= 0 && b < kTuneBuckets && q >= NF_Q_MIN && q <= NF_Q_MAX) c.tuned_q[b] = q;
+    std::string line;
+    while (std::getline(in, line)) {
+        int b = -1, q = 0, t = 0;
+        const int got = sscanf(line.c_str(), "%d %d %d", &b, &q, &t);
+        if (got < 2 || b < 0 || b >= kTuneBuckets || q < NF_Q_MIN || q > NF_Q_MAX) continue;
+        c.tuned_q[b] = q;
+        if (got == 3 && t > 0 && t <= (1 << 20)) c.tuned_target[b] = t;
+    }
 }
 
 static void save_tune_file()
@@ -694,7 +714,7 @@ static void save_tune_file()
     if (!path) return;
     std::ofstream out(path);
     for (int b = 0; b < kTuneBuckets; ++b)
-        if (ctx().tuned_q[b]) out << b << " " << ctx().tuned_q[b] << "\n";
+        if (ctx().tuned_q[b]) out << b << " " << ctx().tuned_q[b] << " " << ctx().tuned_target[b] << "\n";
 }
 
 int autotune_lookup(int n)
@@ -720,31 +740,46 @@ int autotune_run(int n, int qmin, int qmax, int reps)
         x = x * 6364136223846793005ull + 1442695040888963407ull;
         codes[i] = (uint8_t)(x >> 62);
     }
-    int best_q = kDefaultQ;
-    float best_ms = 1e30f;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     StreamFence fence{c.stream};  // the uploads read `codes`
-    for (int q = qmin; q <= qmax; ++q) {
+    // time `reps` fills of the plan for (q, target) after one warm-up fill
+    auto time_plan = [&](int q, int target, float* ms) -> int {
         Plan* p = nullptr;
-        if ((rc = single_plan(n, q, &p))) break;
+        int r = single_plan(n, q, &p, target);
+        if (r) return r;
         const Geom& g = p->geom[0];
         if (hipMemcpyAsync((char*)p->arena.p + g.codes_off, codes.data(), n, hipMemcpyHostToDevice, c.stream) !=
-            hipSuccess) {
-            rc = fail(NF_E_DEVICE, "autotune upload failed");
-            break;
-        }
-        if ((rc = plan_enqueue(*p, c.stream))) break;  // warm-up (and graph capture)
+            hipSuccess)
+            return fail(NF_E_DEVICE, "autotune upload failed");
+        if ((r = plan_enqueue(*p, c.stream))) return r;  // warm-up (and graph capture)
         (void)hipEventRecord(e0, c.stream);
-        for (int r = 0; r < reps && !rc; ++r) rc = plan_enqueue(*p, c.stream);
+        for (int k = 0; k < reps && !r; ++k) r = plan_enqueue(*p, c.stream);
         (void)hipEventRecord(e1, c.stream);
         (void)hipEventSynchronize(e1);
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (!rc && ms < best_ms) {
+        *ms = 0;
+        (void)hipEventElapsedTime(ms, e0, e1);
+        return r;
+    };
+    // q at the default chunk target, then the chunk target at that q; the
+    // default comes first, so a tie keeps it
+    int best_q = kDefaultQ, best_t = kDefaultTarget;
+    float best_ms = 1e30f, ms = 0;
+    for (int q = qmin; q <= qmax && !rc; ++q) {
+        if ((rc = time_plan(q, kDefaultTarget, &ms))) break;
+        if (ms < best_ms) {
             best_ms = ms;
             best_q = q;
+        }
+    }
+    best_ms = 1e30f;
+    for (int t : {kDefaultTarget, 256, 512, 2048}) {
+        if (rc) break;
+        if ((rc = time_plan(best_q, t, &ms))) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_t = t;
         }
     }
     (void)hipEventDestroy(e0);
@@ -752,6 +787,7 @@ int autotune_run(int n, int qmin, int qmax, int reps)
     if (rc) return rc;
     load_tune_file();
     c.tuned_q[bucket_of(n)] = best_q;
+    c.tuned_target[bucket_of(n)] = best_t;
     save_tune_file();
     return best_q;
 }

@@ -80,6 +80,7 @@ struct Plan {
     int q = 8;
     int mode = kModeStaged;
     bool plain = false;  // between-group work by the plain recurrence (NF_BETWEEN=plain)
+    int target = 0;      // between chunks per wavefront step the schedule was built for
     std::vector<Geom> geom;
     std::vector<FoldDesc> h_folds;
     Schedule sc;
@@ -95,6 +96,7 @@ struct Plan {
 
 constexpr int kTuneBuckets = 10;  // n < 256, < 512, ..., >= 65536
 constexpr int kDefaultQ = 8;
+constexpr int kDefaultTarget = 1024;  // between chunks per step: 4 workgroups per CU
 
 struct Context {
     bool ready = false;
@@ -108,6 +110,7 @@ struct Context {
     DevBuf R[NF_Q_MAX + 1];
     std::vector<std::pair<long long, std::unique_ptr<Plan>>> plans;  // LRU, most recent last
     int tuned_q[kTuneBuckets] = {0};
+    int tuned_target[kTuneBuckets] = {0};
     bool tune_loaded = false;
 };
 
@@ -123,7 +126,7 @@ void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, in
                     std::vector<BetweenItem>& out, int* next_slot,
                     std::vector<std::vector<std::pair<int, int>>>& pending);
 void build_schedule(const std::vector<int>& NTs, int target, Schedule& sc);
-int between_target(int mode);
+int between_target(int n_single);
 int plan_allocate(Plan& p);
 TileWork to_work(const TileItem& it, const std::vector<FoldDesc>& fd, int32_t* acc_base);
 BetweenWork to_work(const BetweenItem& it, const std::vector<FoldDesc>& fd, int32_t* acc_base);
@@ -135,8 +138,8 @@ int plan_mode_for(const std::vector<int>& NTs);
 // only for 64-post tiles (q = 1, 2, 4, 8), ignored otherwise.
 bool plain_between_for(int q);
 int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out);
-int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out);
-int single_plan(int n, int q, Plan** out);
+int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out, int target = 0);
+int single_plan(int n, int q, Plan** out, int target = 0);
 int autotune_lookup(int n);
 int autotune_run(int n, int qmin, int qmax, int reps);
 

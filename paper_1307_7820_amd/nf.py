@@ -41,8 +41,8 @@ EXPORTS = [
     "nf_last_error", "nf_init", "nf_shutdown", "nf_precompute_R", "nf_copy_R", "nf_fold", "nf_fold_structure",
     "nf_fold_dev", "nf_batch_create", "nf_batch_run", "nf_batch_scores", "nf_batch_table",
     "nf_batch_info", "nf_batch_structures", "nf_batch_destroy", "nf_fold_batch", "nf_serve_config", "nf_fold_bytes",
-    "nf_submit", "nf_poll", "nf_wait", "nf_poll_ex", "nf_serve_stats", "nf_autotune_q", "nf_autotune",
-    "nf_profile_fold",
+    "nf_submit", "nf_poll", "nf_wait", "nf_poll_ex", "nf_serve_stats", "nf_autotune_q",
+    "nf_autotune_target", "nf_autotune", "nf_profile_fold",
 ]
 
 
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "nf_poll_ex": (c_int, [c_i64, c_int, vp, vp, vp]),
         "nf_serve_stats": (c_int, [ctypes.POINTER(ServeStats)]),
         "nf_autotune_q": (c_int, [c_int]),
+        "nf_autotune_target": (c_int, [c_int]),
         "nf_autotune": (c_int, [c_int, c_int, c_int, c_int]),
         "nf_profile_fold": (c_int, [vp, c_int, c_int, c_int, vp, ctypes.POINTER(KernelProfile)]),
     }
@@ -330,7 +331,13 @@ def nf_autotune_q(n: int) -> int:
     return _check(load().nf_autotune_q(n))
 
 
+def nf_autotune_target(n: int) -> int:
+    """Between-group chunks per wavefront step of a single fold of length n."""
+    return _check(load().nf_autotune_target(n))
+
+
 def nf_autotune(n: int, qmin: int = 4, qmax: int = 8, reps: int = 3) -> int:
+    """Tune q, then the chunk target, at length n; returns the chosen q."""
     return _check(load().nf_autotune(n, qmin, qmax, reps))
 
 

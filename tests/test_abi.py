@@ -165,3 +165,39 @@ def test_serving_submit_and_shutdown_race(lib):
     finally:
         stop.set()
         nf.nf_shutdown()
+
+
+def _tuning_in_subprocess(tmp_path, lines, env_extra, lengths):
+    # the tune file is read once per process: ask a fresh one
+    import json
+    import subprocess
+    import sys
+    f = tmp_path / "tune.txt"
+    f.write_text("".join(l + "\n" for l in lines))
+    env = {k: v for k, v in os.environ.items() if k != "NF_BETWEEN_TARGET"}
+    env.update(NF_AUTOTUNE_CACHE=str(f), **env_extra)
+    code = ("import json,sys; sys.path.insert(0, %r); from paper_1307_7820_amd import nf; "
+            "print(json.dumps([[nf.nf_autotune_q(n), nf.nf_autotune_target(n)] for n in %r]))" % (ROOT, lengths))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def test_tune_file_sets_q_and_chunk_target_per_bucket(tmp_path):
+    # buckets: n < 256 is 0, then one per doubling; 6000 is in bucket 5, 16000 in 6
+    lines = ["5 7 256", "6 8", "2 4 0", "9 12 512", "junk", "3 5 2048 extra"]
+    got = _tuning_in_subprocess(tmp_path, lines, {}, [6000, 16000, 700, 300, 100])
+    assert got[0] == [7, 256]      # both columns
+    assert got[1] == [8, 1024]     # no target column: the default
+    assert got[2] == [4, 1024]     # target 0: the default
+    assert got[3] == [8, 1024]     # q = 12 is out of range: the whole line is ignored
+    assert got[4] == [8, 1024]     # no line for bucket 0
+    lines = ["5 7 256"]
+    got = _tuning_in_subprocess(tmp_path, lines, {"NF_BETWEEN_TARGET": "333"}, [6000, 100])
+    assert got == [[7, 333], [8, 333]]  # the environment overrides every target
+
+
+def test_autotune_target_rejects_bad_length(lib):
+    from paper_1307_7820_amd import nf
+    assert lib.nf_autotune_target(-1) == nf.NF_E_INVAL
+    assert lib.nf_autotune_target(nf.NF_MAX_N + 1) == nf.NF_E_INVAL

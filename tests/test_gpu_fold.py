@@ -161,6 +161,7 @@ def test_autotune_picks_and_caches(nf):
     q = nf.nf_autotune(1500, 4, 8, 1)
     assert 4 <= q <= 8
     assert nf.nf_autotune_q(1500) == q
+    assert nf.nf_autotune_target(1500) in (1024, 256, 512, 2048)
     # a fold with q = 0 uses the tuned value and still matches the oracle
     s = gen.iid_sequence(1500, [111, 0])
     score, T = nf.nf_fold(s, q=0, table=True)
@@ -182,3 +183,24 @@ def test_results_independent_of_stale_device_memory(nf):
             s = gen.iid_sequence(n, [112, q, k])
             score, T = nf.nf_fold(s, q=q, table=True)
             assert np.array_equal(T, oracle.fold_table(s)), (q, n)
+
+
+def test_chunk_targets_give_the_same_table(nf):
+    # The chunk target only changes how each step's between-group work is cut
+    # into workgroups (one store per tile, or chunks combined by atomic max):
+    # every cut gives the oracle's table.
+    old = os.environ.get("NF_BETWEEN_TARGET")
+    seqs = [gen.iid_sequence(n, [311, n]) for n in (2500, 1000)]
+    want = [oracle.fold_table(s) for s in seqs]
+    try:
+        for t in (1, 256, 2048, 65536):
+            os.environ["NF_BETWEEN_TARGET"] = str(t)
+            assert nf.nf_autotune_target(2500) == t
+            for s, w in zip(seqs, want):
+                score, T = nf.nf_fold(s, q=8, table=True)
+                assert np.array_equal(T, w), (t, len(s))
+    finally:
+        if old is None:
+            os.environ.pop("NF_BETWEEN_TARGET", None)
+        else:
+            os.environ["NF_BETWEEN_TARGET"] = old
