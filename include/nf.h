@@ -161,7 +161,12 @@ int nf_fold_batch(const char* const* seqs, const int* ns, int count, int q,
  * A background engine keeps admitted folds resident on the device and
  * advances every active fold by one tile diagonal per device step; requests
  * that arrive while others run join at the next step when a slot and enough
- * of the device-memory budget are free. */
+ * of the device-memory budget are free.  If a device call of the engine
+ * fails, every request it holds or has queued completes with that error
+ * (NF_E_DEVICE, NF_E_NOMEM), and the next nf_submit starts a new engine.
+ * nf_serve_config, nf_submit and nf_shutdown may be called from any thread;
+ * a request submitted while nf_shutdown runs completes with NF_E_ABORTED or
+ * is served by the next engine. */
 
 /* Configure before the first nf_submit (or after nf_shutdown):
  * hbm_budget_bytes = device bytes the active folds may hold together
