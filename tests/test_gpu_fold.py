@@ -92,6 +92,19 @@ def test_n6000_full_table(nf):
         assert np.array_equal(T, want), q
 
 
+def test_n6000_full_table_as_benched(nf):
+    # the launch shape the benchmark times: q and the chunk target tuned the
+    # same way first, then the fold with q = 0
+    if os.environ.get("NF_BETWEEN_TARGET"):
+        pytest.skip("NF_BETWEEN_TARGET fixes the chunk target")
+    s = gen.workload_n6000()
+    q = nf.nf_autotune(len(s), 4, 8, 5)
+    assert nf.nf_autotune_q(len(s)) == q
+    assert nf.nf_autotune_target(len(s)) in (1024, 256, 512, 2048)
+    score, T = nf.nf_fold(s, q=0, table=True)
+    assert np.array_equal(T, oracle.fold_table(s))
+
+
 def test_n16000_full_table(nf):
     s = gen.workload_n16000()
     score, T = nf.nf_fold(s, q=8, table=True)
