@@ -211,11 +211,16 @@ int nf_wait(int64_t ticket, int timeout_ms, int32_t* score_out, int16_t* S_out);
 int nf_poll_ex(int64_t ticket, int timeout_ms, int32_t* score_out, int16_t* S_out, char* db_out);
 
 /* Engine counters: admitted, completed, rejected requests, device steps run,
- * and the largest number of budget bytes ever held by active folds. */
+ * the largest number of budget bytes ever held by active folds, and how many
+ * steps ran fused (one launch per q holding the step's finishes and between
+ * work, as nf_fold does; the others ran staged, on two streams).  A step is
+ * fused while it holds at most 208 tiles to finish, unless NF_MODE (read when
+ * the engine starts) forces one form. */
 typedef struct {
     int64_t submitted, admitted, completed, rejected, steps;
     int64_t active, pending;
     size_t budget_bytes, peak_bytes;
+    int64_t steps_fused;
 } nf_serve_stats_t;
 int nf_serve_stats(nf_serve_stats_t* out);
 

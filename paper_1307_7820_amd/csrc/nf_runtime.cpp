@@ -279,12 +279,7 @@ void build_schedule(const std::vector<int>& NTs, int target, Schedule& sc)
 
 // Execution of a new plan.  NF_MODE = "staged" or "fused" forces one (see
 // PlanMode); otherwise fused steps for one fold and for batches whose steps
-// hold few tiles (one launch and no cross-stream wait per step is cheapest),
-// staged steps for large batches (many folds' tiles and chunks per step fill
-// the device on two streams).  Measured on MI355X: fused is faster for one
-// fold at n = 6000, 12000 and 16000 (2.19 / 6.94 / 13.6 ms against 3.07 /
-// 8.19 / 14.6 ms), staged for a batch of 4096 folds (21.2 against 22.6 ms).
-constexpr long long kFusedMaxTilesPerSide = 208;
+// hold few tiles (kFusedMaxTilesPerSide).
 
 bool plain_between_for(int q)
 {

@@ -76,6 +76,15 @@ struct Schedule {
 //           waits).
 enum PlanMode { kModeStaged = 0, kModeFused = 1 };
 
+// Fused steps while a step holds at most this many tiles to finish (for a
+// batch: the folds' tiles per side summed, the size of its first step):
+// one launch and no cross-stream wait per step is cheapest there; above it
+// staged steps fill the device on two streams with many folds' tiles and
+// chunks.  Measured on MI355X: fused is faster for one fold at n = 6000,
+// 12000 and 16000 (2.19 / 6.94 / 13.6 ms against 3.07 / 8.19 / 14.6 ms),
+// staged for a batch of 4096 folds (21.2 against 22.6 ms).
+constexpr int kFusedMaxTilesPerSide = 208;
+
 struct Plan {
     int q = 8;
     int mode = kModeStaged;

@@ -375,6 +375,13 @@ void engine_main()
     std::vector<BetweenWork> wbtw;
     std::vector<FoldDesc> wfin;
     const int target = std::max(256, ctx().num_cu * 4);
+    // NF_MODE forces fused or staged steps, as for plans; otherwise a step is
+    // fused while it holds few tiles to finish
+    int force_mode = -1;
+    if (const char* e = getenv("NF_MODE")) {
+        if (strcmp(e, "fused") == 0) force_mode = kModeFused;
+        if (strcmp(e, "staged") == 0) force_mode = kModeStaged;
+    }
 
     for (;;) {
         std::vector<Active*> fresh;
@@ -437,6 +444,7 @@ void engine_main()
         wbtw.clear();
         wfin.clear();
         StepRec rec;
+        bool fused = false;
         long long W = 0;
         for (auto* a : active) {
             const int dd = a->stage + 1;
@@ -537,10 +545,30 @@ void engine_main()
             }
         };
         launch_groups(d_diag, wdiag, 0, D.s1);
-        launch_groups(d_tile, wtile, 1, D.s1);
-        ok = ok && hipStreamWaitEvent(D.s2, D.ev_tile, 0) == hipSuccess;
-        launch_groups(d_btw, wbtw, 2, D.s2);
-        ok = ok && hipEventRecord(D.ev_btw, D.s2) == hipSuccess;
+        fused = force_mode >= 0 ? force_mode == kModeFused : (int)wtile.size() <= kFusedMaxTilesPerSide;
+        if (fused) {
+            // one launch per q on s1 holding the finishes of this step and the
+            // between work of the next diagonals: that work reads only tiles
+            // finished in earlier steps (the previous step's between work on
+            // s2, if any, was waited for above)
+            size_t bt = 0, bb = 0;
+            while (ok && (bt < wtile.size() || bb < wbtw.size())) {
+                const int q = std::min(bt < wtile.size() ? wtile[bt].pad0 : NF_Q_MAX + 1,
+                                       bb < wbtw.size() ? wbtw[bb].pad0 : NF_Q_MAX + 1);
+                size_t et = bt, eb = bb;
+                while (et < wtile.size() && wtile[et].pad0 == q) ++et;
+                while (eb < wbtw.size() && wbtw[eb].pad0 == q) ++eb;
+                ok = launch_stage(q, d_tile + bt, (int)(et - bt), d_btw + bb, (int)(eb - bb), D.R[q], D.s1) ==
+                     hipSuccess;
+                bt = et;
+                bb = eb;
+            }
+        } else {
+            launch_groups(d_tile, wtile, 1, D.s1);
+            ok = ok && hipStreamWaitEvent(D.s2, D.ev_tile, 0) == hipSuccess;
+            launch_groups(d_btw, wbtw, 2, D.s2);
+            ok = ok && hipEventRecord(D.ev_btw, D.s2) == hipSuccess;
+        }
         // finished folds: score (and table) to pinned memory; structures are
         // traced back on s3 once this step's finishes are done, so the next
         // steps on s1 do not wait for them
@@ -609,6 +637,7 @@ void engine_main()
         {
             std::lock_guard<std::mutex> lk(E.mu);
             E.st.steps++;
+            if (fused) E.st.steps_fused++;
         }
         // finished folds leave the active set now; they complete with rec
         active.erase(std::remove_if(active.begin(), active.end(),

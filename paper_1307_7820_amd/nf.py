@@ -57,7 +57,7 @@ class ServeStats(ctypes.Structure):
                 ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
                 ("steps", ctypes.c_int64), ("active", ctypes.c_int64),
                 ("pending", ctypes.c_int64), ("budget_bytes", ctypes.c_size_t),
-                ("peak_bytes", ctypes.c_size_t)]
+                ("peak_bytes", ctypes.c_size_t), ("steps_fused", ctypes.c_int64)]
 
 
 class KernelProfile(ctypes.Structure):

@@ -159,3 +159,52 @@ def test_structures_in_a_mix(nf):
         rc = load.nf_submit(b"ACGU", 4, 8, 4)  # unknown flag
         nf._check(rc)
     assert e.value.code == nf.NF_E_INVAL
+
+
+@pytest.mark.parametrize("mode", ["fused", "staged", None])
+def test_step_forms_equal_oracle(nf, mode):
+    # A step runs fused (one launch per q holding its finishes and the next
+    # diagonals' between work) or staged (two streams); NF_MODE, read when the
+    # engine starts, forces one, and without it small steps are fused.  Mixed
+    # q puts several q groups into one step.
+    import os
+    old = os.environ.get("NF_MODE")
+    if mode is None:
+        os.environ.pop("NF_MODE", None)
+    else:
+        os.environ["NF_MODE"] = mode
+    try:
+        nf.nf_serve_config(0, 64, 0)
+        trace = gen.serving_trace(48, 0.0, seed=(207, 0), short=(50, 400), long=(1500, 3000), p_short=0.7)
+        seqs = [s for _, s in trace] + ["", "GC"]
+        tickets, opts = {}, {}
+        for k, s in enumerate(seqs):
+            q = 5 if k % 3 == 0 else 8
+            wt, ws = k % 4 == 0, k % 4 == 1
+            t = nf.nf_submit(s, q=q, want_table=wt, want_structure=ws)
+            tickets[t] = s
+            opts[t] = (wt, ws)
+        for t, s in tickets.items():
+            wt, ws = opts[t]
+            done, score, S, db = nf.nf_poll_ex(t, 120000, len(s), wt, ws)
+            assert done and score == oracle.fold_score(s), len(s)
+            if wt:
+                assert np.array_equal(S, oracle.fold_table(s)), len(s)
+            if ws:
+                assert db == oracle.structure(s), len(s)
+        st = nf.nf_serve_stats()
+        assert st.completed == len(seqs)
+        if mode == "fused":
+            assert st.steps_fused == st.steps
+        elif mode == "staged":
+            assert st.steps_fused == 0
+        else:
+            # the first steps hold every fold's first diagonals (far more than
+            # 208 tiles); the last ones only the longest folds'
+            assert 0 < st.steps_fused < st.steps
+    finally:
+        nf.nf_shutdown()
+        if old is None:
+            os.environ.pop("NF_MODE", None)
+        else:
+            os.environ["NF_MODE"] = old
