@@ -238,7 +238,8 @@ int nf_autotune_q(int n);
 /* The launch shape of a single fold of length n: the number of between-group
  * chunks (workgroups) each wavefront step is cut into (default 1024; the
  * environment variable NF_BETWEEN_TARGET, if set, overrides it and every
- * tuned value).  Batches use the default.  NF_E_INVAL for n out of range. */
+ * tuned value).  Batches and the serving engine's steps use the default (or
+ * NF_BETWEEN_TARGET).  NF_E_INVAL for n out of range. */
 int nf_autotune_target(int n);
 /* Time the fill at length n (reps folds each, after one warm-up fold): first
  * q in qmin..qmax at the default target, then the targets 1024, 256, 512 and

@@ -374,7 +374,8 @@ void engine_main()
     std::vector<TileWork> wdiag, wtile;
     std::vector<BetweenWork> wbtw;
     std::vector<FoldDesc> wfin;
-    const int target = std::max(256, ctx().num_cu * 4);
+    // between chunks per step over all active folds (NF_BETWEEN_TARGET overrides)
+    const int target = between_target(-1);
     // NF_MODE forces fused or staged steps, as for plans; otherwise a step is
     // fused while it holds few tiles to finish
     int force_mode = -1;
