@@ -126,7 +126,7 @@ def roofline(nf, codes, n, q, reps=3):
     from the work lists; duration = the kernel's own start and end, recorded
     into HIP events by its dispatch on the launching stream."""
     prof = nf.nf_profile_fold(codes, n, q, reps)
-    target = nf.nf_autotune_target(n)  # the chunks per step the profiled plan was built with
+    target = nf.nf_autotune_target(n, q)  # the chunks per step the profiled plan was built with
     ks = [i for i in range(len(nf.KERNEL_NAMES)) if prof.launches[i] > 0]
     k = max(ks, key=lambda i: prof.ms[i])
     name = nf.KERNEL_NAMES[k]
@@ -433,7 +433,7 @@ def run_only(args, torch, gen, nf):
     q = args.q if args.q else 8
     ms, wall, score, _ = time_fold(nf, torch, seq, q, args.steps, args.warmup)
     print(json.dumps({"only": args.only, "n": len(seq), "q": q,
-                      "between_chunks_per_step": nf.nf_autotune_target(len(seq)), "ms_per_fold": ms / args.steps,
+                      "between_chunks_per_step": nf.nf_autotune_target(len(seq), q), "ms_per_fold": ms / args.steps,
                       "gcups": cells(len(seq)) * args.steps / (ms / 1e3) / 1e9, "score": score}))
 
 
@@ -472,7 +472,7 @@ def main():
         q = nf.nf_autotune(n, 4, 8, TUNE_REPS)
         log("bench: autotune n=%d: q=%d, chunk target %d (%.2f s)"
             % (n, q, nf.nf_autotune_target(n), time.perf_counter() - t0))
-    target = nf.nf_autotune_target(n)
+    target = nf.nf_autotune_target(n, q)
     log("bench: n=%d q=%d target=%d warmup=%d steps=%d" % (n, q, target, args.warmup, args.steps))
     ms, wall, score, codes = time_fold(nf, torch, seq, q, args.steps, args.warmup)
     ms_per = ms / args.steps

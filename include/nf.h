@@ -235,12 +235,14 @@ int nf_serve_stats(nf_serve_stats_t* out);
  * The q that q = 0 resolves to for sequences of length n (group width of
  * Eq. 3; default 8). */
 int nf_autotune_q(int n);
-/* The launch shape of a single fold of length n: the number of between-group
- * chunks (workgroups) each wavefront step is cut into (default 1024; the
- * environment variable NF_BETWEEN_TARGET, if set, overrides it and every
- * tuned value).  Batches and the serving engine's steps use the default (or
- * NF_BETWEEN_TARGET).  NF_E_INVAL for n out of range. */
-int nf_autotune_target(int n);
+/* The launch shape of a single fold of length n at group width q (0 = what
+ * q = 0 resolves to): the number of between-group chunks (workgroups) each
+ * wavefront step is cut into.  The tuned target of n's bucket applies only
+ * to the q tuned with it; otherwise, and for batches and the serving
+ * engine's steps, the default 1024.  The environment variable
+ * NF_BETWEEN_TARGET, if set, overrides every value.  NF_E_INVAL for n or q
+ * out of range. */
+int nf_autotune_target(int n, int q);
 /* Time the fill at length n (reps folds each, after one warm-up fold): first
  * q in qmin..qmax at the default target, then the targets 1024, 256, 512 and
  * 2048 at the fastest q.  Records both in the in-memory cache (and in the

@@ -438,12 +438,14 @@ int nf_autotune_q(int n)
     return resolve_q(0, n);
 }
 
-int nf_autotune_target(int n)
+int nf_autotune_target(int n, int q)
 {
     std::lock_guard<std::recursive_mutex> lk(g_api);
     clear_error();
     if (n < 0 || n > NF_MAX_N) return fail(NF_E_INVAL, "length %d out of range", n);
-    return between_target(n);
+    int rc = check_q(q);
+    if (rc) return rc;
+    return between_target(n, q);
 }
 
 int nf_autotune(int n, int qmin, int qmax, int reps)

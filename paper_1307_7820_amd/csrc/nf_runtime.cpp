@@ -166,17 +166,20 @@ static int bucket_of(int n);
 static void load_tune_file();
 
 // Between chunks per wavefront step: NF_BETWEEN_TARGET if set; else, for a
-// single fold (n_single >= 0), the autotuned value of its length bucket; else
-// enough workgroups to fill the device.
-int between_target(int n_single)
+// single fold (n_single >= 0) at the q tuned for its length bucket (or q = 0,
+// which resolves to it), the target tuned with that q; else enough
+// workgroups to fill the device.  A target is tuned for one q only: another
+// q has another amount of between work per step.
+int between_target(int n_single, int q)
 {
     const char* e = getenv("NF_BETWEEN_TARGET");
     const int env = e ? atoi(e) : 0;
     if (env > 0) return env;
     if (n_single >= 0) {
         load_tune_file();
-        const int t = ctx().tuned_target[bucket_of(n_single)];
-        if (t > 0) return t;
+        const int b = bucket_of(n_single);
+        const int t = ctx().tuned_target[b];
+        if (t > 0 && (q == 0 || q == ctx().tuned_q[b])) return t;
     }
     return kDefaultTarget;
 }
@@ -615,7 +618,7 @@ int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out, int
     p->mode = plan_mode_for(NTs);
     p->plain = plain_between_for(q);
     if (p->plain) p->mode = kModeStaged;  // the fused step has the lookup built in
-    p->target = target > 0 ? target : between_target(ns.size() == 1 ? ns[0] : -1);
+    p->target = target > 0 ? target : between_target(ns.size() == 1 ? ns[0] : -1, q);
     build_schedule(NTs, p->target, p->sc);
     int rc = plan_allocate(*p);
     if (rc) return rc;
@@ -628,7 +631,7 @@ int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out, int
 int single_plan(int n, int q, Plan** out, int target)
 {
     Context& c = ctx();
-    if (target <= 0) target = between_target(n);
+    if (target <= 0) target = between_target(n, q);
     // NF_MODE and NF_BETWEEN are read when a plan is made, so they are part of the key
     const char* me = getenv("NF_MODE");
     const int mode_env = !me ? 0 : strcmp(me, "fused") == 0 ? 1 : strcmp(me, "staged") == 0 ? 2 : 0;

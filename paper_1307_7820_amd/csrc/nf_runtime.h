@@ -135,7 +135,7 @@ void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, in
                     std::vector<BetweenItem>& out, int* next_slot,
                     std::vector<std::vector<std::pair<int, int>>>& pending);
 void build_schedule(const std::vector<int>& NTs, int target, Schedule& sc);
-int between_target(int n_single);
+int between_target(int n_single, int q);
 int plan_allocate(Plan& p);
 TileWork to_work(const TileItem& it, const std::vector<FoldDesc>& fd, int32_t* acc_base);
 BetweenWork to_work(const BetweenItem& it, const std::vector<FoldDesc>& fd, int32_t* acc_base);

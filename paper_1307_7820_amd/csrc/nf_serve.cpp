@@ -375,7 +375,7 @@ void engine_main()
     std::vector<BetweenWork> wbtw;
     std::vector<FoldDesc> wfin;
     // between chunks per step over all active folds (NF_BETWEEN_TARGET overrides)
-    const int target = between_target(-1);
+    const int target = between_target(-1, 0);
     // NF_MODE forces fused or staged steps, as for plans; otherwise a step is
     // fused while it holds few tiles to finish
     int force_mode = -1;

@@ -112,7 +112,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "nf_poll_ex": (c_int, [c_i64, c_int, vp, vp, vp]),
         "nf_serve_stats": (c_int, [ctypes.POINTER(ServeStats)]),
         "nf_autotune_q": (c_int, [c_int]),
-        "nf_autotune_target": (c_int, [c_int]),
+        "nf_autotune_target": (c_int, [c_int, c_int]),
         "nf_autotune": (c_int, [c_int, c_int, c_int, c_int]),
         "nf_profile_fold": (c_int, [vp, c_int, c_int, c_int, vp, ctypes.POINTER(KernelProfile)]),
     }
@@ -331,9 +331,10 @@ def nf_autotune_q(n: int) -> int:
     return _check(load().nf_autotune_q(n))
 
 
-def nf_autotune_target(n: int) -> int:
-    """Between-group chunks per wavefront step of a single fold of length n."""
-    return _check(load().nf_autotune_target(n))
+def nf_autotune_target(n: int, q: int = 0) -> int:
+    """Between-group chunks per wavefront step of a single fold of length n at
+    group width q (0: the q that q = 0 resolves to)."""
+    return _check(load().nf_autotune_target(n, q))
 
 
 def nf_autotune(n: int, qmin: int = 4, qmax: int = 8, reps: int = 3) -> int:

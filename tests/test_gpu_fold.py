@@ -175,6 +175,7 @@ def test_autotune_picks_and_caches(nf):
     assert 4 <= q <= 8
     assert nf.nf_autotune_q(1500) == q
     assert nf.nf_autotune_target(1500) in (1024, 256, 512, 2048)
+    assert nf.nf_autotune_target(1500, 5 if q == 4 else 4) == 1024  # tuned for q only
     # a fold with q = 0 uses the tuned value and still matches the oracle
     s = gen.iid_sequence(1500, [111, 0])
     score, T = nf.nf_fold(s, q=0, table=True)
@@ -208,7 +209,7 @@ def test_chunk_targets_give_the_same_table(nf):
     try:
         for t in (1, 256, 2048, 65536):
             os.environ["NF_BETWEEN_TARGET"] = str(t)
-            assert nf.nf_autotune_target(2500) == t
+            assert nf.nf_autotune_target(2500, 8) == t
             for s, w in zip(seqs, want):
                 score, T = nf.nf_fold(s, q=8, table=True)
                 assert np.array_equal(T, w), (t, len(s))
