@@ -360,10 +360,12 @@ def extra_serving(nf, torch, gen, count=600, warm=60, budget=2 << 30):
         th.join()
         return done_t, time.perf_counter() - t_start
 
-    # warm the engine
+    # warm the engine: a few folds, then one untimed saturation pass (its
+    # staging buffers grow to the size a full queue needs)
     ws = [nf.nf_submit(seqs[i], 8) for i in range(warm)]
     for t in ws:
         nf.nf_wait(t, 600000)
+    served_run(None)
     done_t, served_T = served_run(None)
     mu_served = count / served_T
 
@@ -391,7 +393,7 @@ def extra_serving(nf, torch, gen, count=600, warm=60, budget=2 << 30):
         "latency_ms_plain": {"p50": 1e3 * _pct(lat_plain, 50), "p99": 1e3 * _pct(lat_plain, 99)},
         "latency_ms_served": {"p50": 1e3 * _pct(lat_served, 50), "p99": 1e3 * _pct(lat_served, 99)},
         "served_over_plain_throughput": mu_served / mu_plain,
-        "engine_steps": int(st.steps), "peak_bytes": int(st.peak_bytes),
+        "engine_steps": int(st.steps), "engine_steps_fused": int(st.steps_fused), "peak_bytes": int(st.peak_bytes),
     }
 
 
@@ -408,6 +410,10 @@ def run_only(args, torch, gen, nf):
         print(json.dumps({"only": "copy", "bytes_per_copy": x.numel(), "copies": args.warmup + args.steps}))
         return
     nf.nf_init(0)
+    if args.only == "serving":
+        # the serving extra alone (plain FIFO, saturation, open loop)
+        print(json.dumps({"only": "serving", **extra_serving(nf, torch, gen)}))
+        return
     if args.only == "batch":
         seqs = gen.workload_batch4096()
         b = nf.Batch(seqs, q=8)
@@ -446,7 +452,7 @@ def main():
     ap.add_argument("--cpu-budget-s", type=float, default=10.0)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra workloads)")
     ap.add_argument("--only", choices=["n6000", "n16000", "batch", "copy", "structure6000", "structure16000",
-                                       "plain16000"],
+                                       "plain16000", "serving"],
                     help="run one workload K times and print a short line (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
