@@ -185,6 +185,10 @@ struct Device {
         DevBuf dev;
         size_t cap = 0;
         hipEvent_t free_ev = nullptr;
+        // completion of the step that uses this slot; reused, since a slot is
+        // taken again only after that step has retired (at a launch at most
+        // kInflightSteps - 1 steps are in flight, and there is one slot more)
+        hipEvent_t step_ev = nullptr;
         bool used = false;
     } ring[kInflightSteps + 1];
     int32_t* h_scores = nullptr;  // pinned, one per slot
@@ -234,7 +238,10 @@ int engine_init(Engine& E, Device& D)
     HIPCHK(hipHostMalloc((void**)&D.h_scores, sizeof(int32_t) * E.max_slots, hipHostMallocDefault));
     if ((rc = D.d_scores.alloc(sizeof(int32_t) * E.max_slots))) return rc;
     for (int i = E.max_slots - 1; i >= 0; --i) D.free_slots.push_back(i);
-    for (auto& r : D.ring) HIPCHK(hipEventCreateWithFlags(&r.free_ev, hipEventDisableTiming));
+    for (auto& r : D.ring) {
+        HIPCHK(hipEventCreateWithFlags(&r.free_ev, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&r.step_ev, hipEventDisableTiming));
+    }
     return NF_OK;
 }
 
@@ -246,6 +253,7 @@ void engine_release(Device& D)
     for (auto& r : D.ring) {
         if (r.host) (void)hipHostFree(r.host);
         if (r.free_ev) (void)hipEventDestroy(r.free_ev);
+        if (r.step_ev) (void)hipEventDestroy(r.step_ev);
         r.dev.reset();
     }
     if (D.h_scores) (void)hipHostFree(D.h_scores);
@@ -406,7 +414,6 @@ void engine_main()
                     break;
                 }
                 complete(E, D, inflight.front());
-                (void)hipEventDestroy(inflight.front().ev);
                 D.ring[inflight.front().ring].used = false;
                 inflight.pop_front();
                 continue;
@@ -424,7 +431,6 @@ void engine_main()
         while ((int)inflight.size() >= kInflightSteps) {
             if (hipEventSynchronize(inflight.front().ev) != hipSuccess) { rc = NF_E_DEVICE; break; }
             complete(E, D, inflight.front());
-            (void)hipEventDestroy(inflight.front().ev);
             D.ring[inflight.front().ring].used = false;
             inflight.pop_front();
         }
@@ -618,7 +624,7 @@ void engine_main()
         }
         // the step is complete when both streams are through it
         ok = ok && hipStreamWaitEvent(D.s1, D.ev_btw, 0) == hipSuccess;
-        ok = ok && hipEventCreateWithFlags(&rec.ev, hipEventDisableTiming) == hipSuccess;
+        rec.ev = rg.step_ev;
         if (any_tb) {  // ... and the tracebacks on s3
             ok = ok && hipEventRecord(D.ev_end, D.s1) == hipSuccess;
             ok = ok && hipStreamWaitEvent(D.s3, D.ev_end, 0) == hipSuccess;
@@ -651,7 +657,6 @@ void engine_main()
         // opportunistic completion of steps the device has already finished
         while (!inflight.empty() && hipEventQuery(inflight.front().ev) == hipSuccess) {
             complete(E, D, inflight.front());
-            (void)hipEventDestroy(inflight.front().ev);
             D.ring[inflight.front().ring].used = false;
             inflight.pop_front();
         }
@@ -663,7 +668,6 @@ void engine_main()
         } else {
             for (auto* a : r.finishing) active.push_back(a);
         }
-        (void)hipEventDestroy(r.ev);
     }
     inflight.clear();
     const int code = rc ? rc : NF_E_ABORTED;
