@@ -184,7 +184,6 @@ struct Device {
         char* host = nullptr;
         DevBuf dev;
         size_t cap = 0;
-        hipEvent_t free_ev = nullptr;
         // completion of the step that uses this slot; reused, since a slot is
         // taken again only after that step has retired (at a launch at most
         // kInflightSteps - 1 steps are in flight, and there is one slot more)
@@ -239,7 +238,6 @@ int engine_init(Engine& E, Device& D)
     if ((rc = D.d_scores.alloc(sizeof(int32_t) * E.max_slots))) return rc;
     for (int i = E.max_slots - 1; i >= 0; --i) D.free_slots.push_back(i);
     for (auto& r : D.ring) {
-        HIPCHK(hipEventCreateWithFlags(&r.free_ev, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&r.step_ev, hipEventDisableTiming));
     }
     return NF_OK;
@@ -252,7 +250,6 @@ void engine_release(Device& D)
     if (D.s3) (void)hipStreamSynchronize(D.s3);
     for (auto& r : D.ring) {
         if (r.host) (void)hipHostFree(r.host);
-        if (r.free_ev) (void)hipEventDestroy(r.free_ev);
         if (r.step_ev) (void)hipEventDestroy(r.step_ev);
         r.dev.reset();
     }
@@ -521,7 +518,7 @@ void engine_main()
         const size_t nb_d = wdiag.size() * sizeof(TileWork), nb_t = wtile.size() * sizeof(TileWork);
         const size_t nb_b = wbtw.size() * sizeof(BetweenWork), nb_f = wfin.size() * sizeof(FoldDesc);
         const size_t total = nb_d + nb_t + nb_b + nb_f + 64;
-        if (rg.used) (void)hipEventSynchronize(rg.free_ev);
+        if (rg.used) (void)hipEventSynchronize(rg.step_ev);  // never taken: see Ring::step_ev
         if ((rc = ensure_ring(rg, total))) break;
         char* h = rg.host;
         std::memcpy(h, wdiag.data(), nb_d);
@@ -535,8 +532,12 @@ void engine_main()
         const FoldDesc* d_fin = (const FoldDesc*)(dv + nb_d + nb_t + nb_b);
         bool ok = hipMemcpyAsync(dv, h, nb_d + nb_t + nb_b + nb_f, hipMemcpyHostToDevice, D.s1) == hipSuccess;
         // ---- launches
-        ok = ok && hipStreamWaitEvent(D.s1, D.ev_btw, 0) == hipSuccess;  // previous step's between work
-        ok = ok && hipEventRecord(D.ev_tile, D.s1) == hipSuccess;        // previous finishes + items in place
+        // s1 already follows the previous step's between work: a staged step
+        // ends with s1 waiting for s2, a fused one runs it on s1.  A fused
+        // step uses s1 alone; a staged one runs its between work on s2 after
+        // the previous finishes and this step's items are in place.
+        fused = force_mode >= 0 ? force_mode == kModeFused : (int)wtile.size() <= kFusedMaxTilesPerSide;
+        if (!fused) ok = ok && hipEventRecord(D.ev_tile, D.s1) == hipSuccess;
         auto launch_groups = [&](auto* dptr, auto& v, int which, hipStream_t st) {
             size_t b = 0;
             while (ok && b < v.size()) {
@@ -552,7 +553,6 @@ void engine_main()
             }
         };
         launch_groups(d_diag, wdiag, 0, D.s1);
-        fused = force_mode >= 0 ? force_mode == kModeFused : (int)wtile.size() <= kFusedMaxTilesPerSide;
         if (fused) {
             // one launch per q on s1 holding the finishes of this step and the
             // between work of the next diagonals: that work reads only tiles
@@ -623,7 +623,7 @@ void engine_main()
             }
         }
         // the step is complete when both streams are through it
-        ok = ok && hipStreamWaitEvent(D.s1, D.ev_btw, 0) == hipSuccess;
+        if (!fused) ok = ok && hipStreamWaitEvent(D.s1, D.ev_btw, 0) == hipSuccess;
         rec.ev = rg.step_ev;
         if (any_tb) {  // ... and the tracebacks on s3
             ok = ok && hipEventRecord(D.ev_end, D.s1) == hipSuccess;
@@ -632,7 +632,6 @@ void engine_main()
         } else {
             ok = ok && hipEventRecord(rec.ev, D.s1) == hipSuccess;
         }
-        ok = ok && hipEventRecord(rg.free_ev, D.s1) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
             rc = NF_E_DEVICE;
