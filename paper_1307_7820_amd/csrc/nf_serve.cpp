@@ -504,9 +504,11 @@ void engine_main()
                 wfin.push_back(a->fd);
             }
         }
-        // group each list by q (kernels are specialised per q)
+        // group each list by q (kernels are specialised per q); a list of one
+        // q, the usual case, is already in order
         auto by_q = [](auto& v) {
-            std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.pad0 < y.pad0; });
+            auto lt = [](const auto& x, const auto& y) { return x.pad0 < y.pad0; };
+            if (!std::is_sorted(v.begin(), v.end(), lt)) std::stable_sort(v.begin(), v.end(), lt);
         };
         by_q(wdiag);
         by_q(wtile);
