@@ -456,7 +456,7 @@ def main():
                     help="run one workload K times and print a short line (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (a single fold is a "
+        print("bench.py measures one GPU: the library has no multi-GPU path (a single fold is a "
               "latency-bound wavefront; batches and serving shard by fold). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
