@@ -92,41 +92,32 @@ def fold_score(seq: str, nthreads: int = 0) -> int:
 def r_table(q: int, with_index: bool = False):
     """The table R of Section 3.1 for vectors of length q.
 
-    The paper indexes R by the pair (v, v-bar) with v in {0,1}^q and v-bar in
-    {0,-1}^q, where v_0 = v-bar_0 = 0 by definition, so only q-1 entries carry
-    information.  Here both vectors are encoded by their informative entries:
-    bit p-1 of ``h`` is v_p and bit p-1 of ``c`` is -v-bar_p (p = 1..q-1), and
-    the result is an array ``R[h, c]`` of shape (2^(q-1), 2^(q-1)).
+    R pairs a horizontal difference vector v (entries 0 or 1) with a vertical
+    one v-bar (entries 0 or -1) and holds the largest prefix total
+    max_k (V_k + Vbar_k) of Eq. 3, where V_k and Vbar_k are the sums of the
+    first k+1 entries.  Both vectors start with v_0 = v-bar_0 = 0, so only
+    q-1 entries carry information: bit p-1 of ``h`` is v_p and bit p-1 of
+    ``c`` is -v-bar_p (p = 1..q-1).  The result is ``R[h, c]`` of shape
+    (2^(q-1), 2^(q-1)).
 
-    Each entry follows the preprocessing listing: running sums of v and of
-    v-bar over k = 0..q-1, keeping the largest sum total (starting from 0) and,
-    with ``with_index``, the first k at which it is reached (strict '>').
+    Computed from that definition: the prefix sums of the bits of h and of c
+    (with the empty prefix, k = 0, first), their difference, and its maximum
+    over k.  ``with_index`` also returns the smallest maximising k, the index
+    the paper's listing keeps with its strict '>' comparison.
     """
     if not (1 <= q <= 12):
         raise ValueError("q out of range")
     m = q - 1
     size = 1 << m
-    h = np.arange(size, dtype=np.int64)[:, None] * np.ones((1, size), dtype=np.int64)
-    c = np.ones((size, 1), dtype=np.int64) * np.arange(size, dtype=np.int64)[None, :]
-    max_val = np.zeros((size, size), dtype=np.int64)
-    max_idx = np.zeros((size, size), dtype=np.int64)
-    sum1 = np.zeros((size, size), dtype=np.int64)
-    sum2 = np.zeros((size, size), dtype=np.int64)
-    for k in range(q):
-        if k >= 1:
-            v_k = (h >> (k - 1)) & 1           # horizontal difference v_k in {0, 1}
-            vbar_k = -((c >> (k - 1)) & 1)     # vertical difference v-bar_k in {0, -1}
-        else:
-            v_k = np.zeros_like(h)             # v_0 = 0
-            vbar_k = np.zeros_like(c)          # v-bar_0 = 0
-        sum1 = sum1 + v_k
-        sum2 = sum2 + vbar_k
-        better = (sum1 + sum2) > max_val
-        max_val = np.where(better, sum1 + sum2, max_val)
-        max_idx = np.where(better, k, max_idx)
-    R = max_val.astype(np.uint8)
+    words = np.arange(size, dtype=np.int64)
+    bits = (words[:, None] >> np.arange(m, dtype=np.int64)[None, :]) & 1      # [word, p-1]
+    prefix = np.zeros((size, q), dtype=np.int16)                              # [word, k], k = 0..q-1
+    prefix[:, 1:] = np.cumsum(bits, axis=1)
+    # V_k + Vbar_k for every (h, c, k): prefix of h's bits minus prefix of c's
+    totals = prefix[:, None, :] - prefix[None, :, :]
+    R = totals.max(axis=2).astype(np.uint8)
     if with_index:
-        return R, max_idx.astype(np.uint8)
+        return R, np.argmax(totals, axis=2).astype(np.uint8)  # argmax: first maximum
     return R
 
 
