@@ -23,9 +23,18 @@ namespace nf {
 
 namespace {
 
-// Address-space views of generic pointers: row words are wave-uniform and
-// read-only while a kernel runs, so they go through the scalar cache
-// (constant address space); column words are per-lane global loads.
+// Address-space views of generic pointers.  The between-group lookups read
+// row words wave-uniformly through the scalar cache (constant address
+// space); column words are per-lane global loads.  The scalar cache is not
+// kept coherent with vector stores inside a launch, so the invariant is: no
+// row word that a launch reads through the scalar cache is written by that
+// same launch.  It holds because a between chunk of tile (A, A+d) reads only
+// tiles of diagonals 2 .. d-2, a staged between launch writes no packed
+// words (the finishes of diagonal d-1 that may run beside it on another
+// stream write only that diagonal), and the fused step that runs it
+// (d = s+1) writes only the words of diagonal s.  Packed blocks of different
+// tiles never share a cache line (each block is a multiple of 256 bytes).
+// The tile finish reads every packed word through vector loads.
 #define NF_GLOBAL __attribute__((address_space(1)))
 #define NF_CONST __attribute__((address_space(4)))
 template <class T>
@@ -354,16 +363,26 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     wait_pre();
     constexpr int RSZ = 1 << (2 * M);
     uint8_t rbyte = 0;
+    uint4 rvec = make_uint4(0u, 0u, 0u, 0u);
     if constexpr (kLoadR) {
-        if constexpr (RSZ >= 16) {
+        if constexpr (RSZ >= 1024) {
             // R goes global -> LDS by DMA (no registers, no LDS store): lane l
-            // of a wave lands at the wave's base + 16 l
+            // of a wave lands at the wave's base + 16 l.  One wave moves 1 KB,
+            // and RSZ is a multiple of 1 KB here, so no lane reads past R or
+            // writes past Rl.
 #pragma unroll
             for (int u = 0; u < (RSZ + kTileThreads * 16 - 1) / (kTileThreads * 16); ++u) {
                 const int base = (u * kTileThreads + wave * 64) * 16;  // wave-uniform
                 if (base < RSZ)
                     __builtin_amdgcn_global_load_lds((const NF_GLOBAL void*)(Rg + base + lane * 16),
                                                      (__attribute__((address_space(3))) void*)(Rl + base), 16, 0, 0);
+            }
+        } else if constexpr (RSZ >= 16) {
+            // 16 .. 256 bytes: one 16-byte load per lane that holds a piece,
+            // stored to LDS with the other prologue stores
+            if (tid * 16 < RSZ) {
+                const NF_GLOBAL uint32_t* src = (const NF_GLOBAL uint32_t*)(Rg + tid * 16);
+                rvec = make_uint4(src[0], src[1], src[2], src[3]);
             }
         } else {
             rbyte = ((const NF_GLOBAL uint8_t*)Rg)[min(tid, RSZ - 1)];
@@ -433,6 +452,8 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     // stores
     if constexpr (kLoadR && RSZ < 16) {
         if (tid < RSZ) Rl[tid] = rbyte;
+    } else if constexpr (kLoadR && RSZ < 1024) {
+        if (tid * 16 < RSZ) *reinterpret_cast<uint4*>(Rl + tid * 16) = rvec;
     }
     if (tid < 64) {
         ca[tid] = cda;
@@ -459,7 +480,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
 #pragma unroll
         for (int b = 0; b < 8; ++b) accp[b * 512] = 0;
     }
-    if constexpr (kLoadR) __builtin_amdgcn_s_waitcnt(0);  // the R transfer (vector memory counter) is done
+    if constexpr (kLoadR && RSZ >= 1024) __builtin_amdgcn_s_waitcnt(0);  // the R transfer (vector memory counter) is done
     __syncthreads();
 
     // ---- row words of tile (A, A) for the block pushes
