@@ -27,7 +27,8 @@
  *        S_out[i*n + j] = D(i+1, j+1) for i <= j, and 0 for i > j.
  *  - Inputs are borrowed for the duration of the call (nf_submit copies);
  *    outputs are caller-allocated.  Device memory the library needs is
- *    allocated and owned by the library and released by nf_shutdown().
+ *    allocated and owned by the library (through nf_set_allocator's hook if
+ *    one is set, else hipMalloc) and released by nf_shutdown().
  *  - Host functions are thread-safe; calls are serialised internally.
  *  - No GPU fallback: without a usable gfx950 device every call that needs
  *    the GPU returns NF_E_DEVICE.
@@ -71,6 +72,27 @@ int nf_init(int device);
  * engine (pending tickets then report NF_E_ABORTED).  The library can be used
  * again afterwards. */
 void nf_shutdown(void);
+
+/* Device memory hook.  Every device buffer the library holds (fold and batch
+ * workspaces, R, the serving arena, traceback scratch) is taken from
+ * alloc(bytes, ctx), which must return device memory of the library's device
+ * aligned to 256 bytes, or NULL (the call that needed it then fails with
+ * NF_E_NOMEM).  A buffer goes back through the free_(ptr, ctx) of the hook it
+ * came from, after the library has waited for the device to be idle, so the
+ * owner may reuse the block at once.  Both NULL restores hipMalloc/hipFree for
+ * later allocations.  Buffers already held keep their own hook, so the hook
+ * may be changed at any time; the functions must stay callable until
+ * nf_shutdown() has returned and every batch is destroyed.  They may be
+ * called from the serving engine's thread.  NF_E_INVAL when exactly one of
+ * the two is NULL.  Host code only: no device is needed to set it. */
+int nf_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_)(void* ptr, void* ctx), void* ctx);
+
+/* Base codes of Section 2's alphabet: codes_out[i] = 0, 1, 2, 3 for seq[i] =
+ * A, C, G, U (lower case accepted), the encoding nf_fold_dev takes; a pair
+ * is complementary exactly when its two codes add up to 3.  NF_E_INVAL at the
+ * first other byte (its position is in nf_last_error()), and then codes_out
+ * is left untouched.  Host code only. */
+int nf_encode(const char* seq, int n, uint8_t* codes_out);
 
 /* ---- Four-Russians table R (Section 3.1, preprocessing listing; Eq. 3) ----
  * Builds R for vectors of length q on the device, once per q (cached;

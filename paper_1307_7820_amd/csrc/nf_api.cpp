@@ -59,6 +59,28 @@ void nf_shutdown(void)
     c.ready = false;
 }
 
+int nf_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx)
+{
+    clear_error();
+    AllocHook h;
+    h.alloc = alloc;
+    h.free_ = free_;
+    h.ctx = alloc ? ctx : nullptr;
+    return set_allocator(h);
+}
+
+int nf_encode(const char* seq, int n, uint8_t* codes_out)
+{
+    clear_error();
+    int rc = check_length(n);
+    if (rc) return rc;
+    if (n > 0 && (!seq || !codes_out)) return fail(NF_E_INVAL, "NULL argument");
+    std::vector<uint8_t> tmp(n);
+    if ((rc = encode_sequence(seq, n, tmp.data()))) return rc;
+    std::copy(tmp.begin(), tmp.end(), codes_out);
+    return NF_OK;
+}
+
 int nf_precompute_R(int q)
 {
     std::lock_guard<std::recursive_mutex> lk(g_api);

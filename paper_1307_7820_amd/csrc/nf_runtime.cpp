@@ -43,17 +43,58 @@ void clear_error() { g_err.clear(); }
 
 // ------------------------------------------------------------------ device memory
 
+static std::mutex g_hook_mu;
+static AllocHook g_hook;
+
+int set_allocator(const AllocHook& h)
+{
+    if ((h.alloc == nullptr) != (h.free_ == nullptr))
+        return fail(NF_E_INVAL, "nf_set_allocator needs both functions, or neither");
+    std::lock_guard<std::mutex> lk(g_hook_mu);
+    g_hook = h;
+    return NF_OK;
+}
+
+static AllocHook current_hook()
+{
+    std::lock_guard<std::mutex> lk(g_hook_mu);
+    return g_hook;
+}
+
 DevBuf::~DevBuf() { reset(); }
 void DevBuf::reset()
 {
-    if (p) (void)hipFree(p);
+    if (p) {
+        if (from.free_) {
+            // the owner of a hooked allocator may hand the block out again at
+            // once (a caching allocator does): no kernel may still use it
+            (void)hipDeviceSynchronize();
+            from.free_(p, from.ctx);
+        } else {
+            (void)hipFree(p);
+        }
+    }
     p = nullptr;
     bytes = 0;
+    from = AllocHook{};
 }
 int DevBuf::alloc(size_t nbytes)
 {
     reset();
     if (nbytes == 0) return NF_OK;
+    const AllocHook h = current_hook();
+    if (h.alloc) {
+        p = h.alloc(nbytes, h.ctx);
+        if (!p) return fail(NF_E_NOMEM, "allocator hook returned NULL for %zu bytes", nbytes);
+        if ((uintptr_t)p & 255) {
+            h.free_(p, h.ctx);
+            p = nullptr;
+            return fail(NF_E_INVAL, "allocator hook returned an address not aligned to 256 bytes");
+        }
+        from = h;
+        bytes = nbytes;
+        return NF_OK;
+    }
     hipError_t e = hipMalloc(&p, nbytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();

@@ -38,10 +38,20 @@ struct StreamFence {
     }
 };
 
-// Owned device allocation.
+// Device memory hook (nf_set_allocator): null members mean hipMalloc/hipFree.
+struct AllocHook {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*free_)(void*, void*) = nullptr;
+    void* ctx = nullptr;
+};
+int set_allocator(const AllocHook& h);
+
+// Owned device allocation, taken from the hook in force when it is
+// allocated and given back through that same hook.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    AllocHook from;  // the hook p came from
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;

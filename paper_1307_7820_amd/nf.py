@@ -1,7 +1,10 @@
 """Thin ctypes binding of libnf.so (include/nf.h), names as in the C ABI.
 
 Marshalling only: every step of a fold runs in the library's HIP kernels.
-PyTorch supplies device memory and streams for the ``*_dev`` variants.
+PyTorch supplies device memory and streams: once the library is loaded, its
+device buffers come from torch's caching allocator through the library's
+allocator hook (``nf_set_allocator``; set NF_TORCH_ALLOCATOR=0 to keep
+hipMalloc), and the ``*_dev`` variants run on torch streams.
 The binding raises ``NFError`` for every negative return code and fails loudly
 when the library is missing: there is no CPU fallback.
 """
@@ -38,7 +41,8 @@ _CODE_NAMES = {
 
 # every symbol include/nf.h declares
 EXPORTS = [
-    "nf_last_error", "nf_init", "nf_shutdown", "nf_precompute_R", "nf_copy_R", "nf_fold", "nf_fold_structure",
+    "nf_last_error", "nf_init", "nf_shutdown", "nf_set_allocator", "nf_encode",
+    "nf_precompute_R", "nf_copy_R", "nf_fold", "nf_fold_structure",
     "nf_fold_dev", "nf_batch_create", "nf_batch_run", "nf_batch_scores", "nf_batch_table",
     "nf_batch_info", "nf_batch_structures", "nf_batch_destroy", "nf_fold_batch", "nf_serve_config", "nf_fold_bytes",
     "nf_submit", "nf_poll", "nf_wait", "nf_poll_ex", "nf_serve_stats", "nf_autotune_q",
@@ -91,6 +95,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "nf_last_error": (ctypes.c_char_p, []),
         "nf_init": (c_int, [c_int]),
         "nf_shutdown": (None, []),
+        "nf_set_allocator": (c_int, [vp, vp, vp]),
+        "nf_encode": (c_int, [ctypes.c_char_p, c_int, vp]),
         "nf_precompute_R": (c_int, [c_int]),
         "nf_copy_R": (c_int, [c_int, vp, c_sz]),
         "nf_fold": (c_int, [ctypes.c_char_p, c_int, c_int, vp]),
@@ -121,7 +127,82 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         fn.restype = res
         fn.argtypes = args
     _lib = L
+    if os.environ.get("NF_TORCH_ALLOCATOR", "1") != "0":
+        use_torch_allocator()
     return L
+
+
+# ---------------------------------------------------------------- device memory
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+# Every hook ever installed stays referenced: a buffer goes back through the
+# hook it came from, which may be an earlier one.
+_hooks: list = []
+_live_batches = None  # weakref.WeakSet of Batch objects, closed at exit
+_exit_registered = False
+
+
+def nf_set_allocator(alloc=None, free=None) -> None:
+    """Install a device memory hook: ``alloc(nbytes) -> address`` (0 on
+    failure) and ``free(address)``; both None restores hipMalloc/hipFree."""
+    L = load()
+    if alloc is None and free is None:
+        _check(L.nf_set_allocator(None, None, None))
+        return
+    if alloc is None or free is None:
+        raise ValueError("nf_set_allocator needs both functions, or neither")
+
+    def a(nbytes, ctx):
+        try:
+            return int(alloc(int(nbytes))) or None
+        except Exception:
+            return None  # the library reports NF_E_NOMEM
+
+    def f(ptr, ctx):
+        free(int(ptr))
+
+    fa, ff = _ALLOC_FN(a), _FREE_FN(f)
+    _hooks.append((fa, ff))
+    _check(L.nf_set_allocator(ctypes.cast(fa, ctypes.c_void_p), ctypes.cast(ff, ctypes.c_void_p), None))
+    _register_exit()
+
+
+def use_torch_allocator() -> None:
+    """Let torch's caching allocator supply every device buffer of the
+    library (on the library's device and the calling thread's current torch
+    stream; the library waits for the device before it hands a block back)."""
+    import torch
+
+    def alloc(nbytes):
+        return torch.cuda.caching_allocator_alloc(nbytes)
+
+    def free(ptr):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    nf_set_allocator(alloc, free)
+
+
+def _register_exit() -> None:
+    """Release the library's buffers while the interpreter (and the hook's
+    Python functions) still run: nf_shutdown and every open batch at exit."""
+    global _exit_registered, _live_batches
+    if _exit_registered:
+        return
+    import atexit
+    import weakref
+    _live_batches = weakref.WeakSet()
+
+    def release():
+        for b in list(_live_batches):
+            try:
+                b.close()
+            except Exception:
+                pass
+        if _lib is not None:
+            _lib.nf_shutdown()
+    atexit.register(release)
+    _exit_registered = True
 
 
 def last_error() -> str:
@@ -181,27 +262,57 @@ def nf_fold_structure(seq, q: int = 0):
     return score, out.raw[:n].decode("ascii")
 
 
+def _dev_ptr(x, dtype_name: str, min_numel: int, what: str):
+    """Device address of a torch tensor argument, after checking that it is a
+    contiguous device tensor of the right dtype holding at least min_numel
+    elements (a raw integer address is passed through unchecked; None stays
+    None)."""
+    if x is None:
+        return None
+    if not hasattr(x, "data_ptr"):
+        return int(x)
+    import torch
+    if not x.is_cuda:
+        raise ValueError("%s must be a device tensor" % what)
+    if x.dtype != getattr(torch, dtype_name):
+        raise ValueError("%s must be %s, not %s" % (what, dtype_name, x.dtype))
+    if not x.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if x.numel() < min_numel:
+        raise ValueError("%s holds %d elements, needs %d" % (what, x.numel(), min_numel))
+    return x.data_ptr()
+
+
+def _stream_handle(stream):
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return stream
+
+
 def nf_fold_dev(d_codes, n: int, q: int = 0, d_score=None, d_S=None, stream=None) -> None:
-    """Asynchronous fold of device codes (torch uint8 tensor or raw pointer)."""
-    def p(x):
-        if x is None:
-            return None
-        return x.data_ptr() if hasattr(x, "data_ptr") else int(x)
-    s = stream
-    if s is not None and hasattr(s, "cuda_stream"):
-        s = s.cuda_stream
-    _check(load().nf_fold_dev(p(d_codes), n, q, p(d_score), p(d_S), s))
+    """Asynchronous fold of device codes (torch uint8 tensor or raw pointer).
+
+    Tensors are checked before the call: d_codes uint8 with >= n elements,
+    d_score int32 with >= 1, d_S int16 with >= n*n; all contiguous, on the
+    device."""
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    pc = _dev_ptr(d_codes, "uint8", n, "d_codes")
+    ps = _dev_ptr(d_score, "int32", 1, "d_score")
+    pS = _dev_ptr(d_S, "int16", n * n, "d_S")
+    _check(load().nf_fold_dev(pc, n, q, ps, pS, _stream_handle(stream)))
 
 
-def encode(seq: str) -> np.ndarray:
-    """Host-side base codes A=0, C=1, G=2, U=3 (for ``nf_fold_dev``)."""
-    lut = np.full(256, 255, dtype=np.uint8)
-    for ch, v in (("A", 0), ("C", 1), ("G", 2), ("U", 3), ("a", 0), ("c", 1), ("g", 2), ("u", 3)):
-        lut[ord(ch)] = v
-    out = lut[np.frombuffer(seq.encode("ascii"), dtype=np.uint8)]
-    if np.any(out == 255):
-        raise ValueError("sequence holds a character outside A, C, G, U")
-    return out
+def nf_encode(seq) -> np.ndarray:
+    """Base codes A=0, C=1, G=2, U=3 of a sequence, by the library
+    (``nf_encode``), as ``nf_fold_dev`` takes them."""
+    b = seq.encode("ascii") if isinstance(seq, str) else bytes(seq)
+    out = np.zeros(max(1, len(b)), dtype=np.uint8)
+    _check(load().nf_encode(b, len(b), out.ctypes.data))
+    return out[: len(b)]
+
+
+encode = nf_encode
 
 
 class Batch:
@@ -216,9 +327,12 @@ class Batch:
         ns = (ctypes.c_int * max(1, self.count))(*[len(s) for s in self._keep])
         self.ns = [len(s) for s in self._keep]
         h = ctypes.c_void_p()
+        self._h = None
         _check(L.nf_batch_create(ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(ns, ctypes.c_void_p),
                                  self.count, q, ctypes.byref(h)))
         self._h = h
+        if _live_batches is not None:
+            _live_batches.add(self)
 
     def run(self, stream=None) -> None:
         s = stream.cuda_stream if stream is not None and hasattr(stream, "cuda_stream") else stream
@@ -344,8 +458,9 @@ def nf_autotune(n: int, qmin: int = 4, qmax: int = 8, reps: int = 3) -> int:
 
 def nf_profile_fold(d_codes, n: int, q: int = 0, reps: int = 1, stream=None) -> KernelProfile:
     """Per-kernel HIP-event timing of the fill of device codes (see nf.h)."""
-    p = d_codes.data_ptr() if hasattr(d_codes, "data_ptr") else int(d_codes)
-    s = stream.cuda_stream if stream is not None and hasattr(stream, "cuda_stream") else stream
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    p = _dev_ptr(d_codes, "uint8", n, "d_codes")
     out = KernelProfile()
-    _check(load().nf_profile_fold(p, n, q, reps, s, ctypes.byref(out)))
+    _check(load().nf_profile_fold(p, n, q, reps, _stream_handle(stream), ctypes.byref(out)))
     return out

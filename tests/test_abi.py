@@ -205,3 +205,69 @@ def test_autotune_target_rejects_bad_length(lib):
     assert lib.nf_autotune_target(-1, 0) == nf.NF_E_INVAL
     assert lib.nf_autotune_target(nf.NF_MAX_N + 1, 0) == nf.NF_E_INVAL
     assert lib.nf_autotune_target(100, 10) == nf.NF_E_INVAL
+
+
+def test_fold_dev_checks_tensor_arguments_before_the_call():
+    """The binding refuses device arguments that are too small, of the wrong
+    dtype, not contiguous or on the host, before the library sees them (an
+    undersized buffer would otherwise be written out of bounds)."""
+    import torch
+    from paper_1307_7820_amd import nf
+    codes = torch.zeros(10, dtype=torch.uint8)
+    with pytest.raises(ValueError, match="device tensor"):
+        nf.nf_fold_dev(codes, 10, 8)
+    with pytest.raises(ValueError):
+        nf.nf_fold_dev(torch.zeros(10, dtype=torch.uint8), -1, 8)
+    # the dtype, size and layout checks read only tensor metadata
+    class Fake:
+        def __init__(self, dtype, numel, contiguous=True):
+            self.dtype, self._n, self._c, self.is_cuda = dtype, numel, contiguous, True
+
+        def numel(self):
+            return self._n
+
+        def is_contiguous(self):
+            return self._c
+
+        def data_ptr(self):
+            raise AssertionError("the pointer must not be taken")
+    with pytest.raises(ValueError, match="uint8"):
+        nf.nf_fold_dev(Fake(torch.int32, 10), 10, 8)
+    with pytest.raises(ValueError, match="needs 10"):
+        nf.nf_fold_dev(Fake(torch.uint8, 9), 10, 8)
+    with pytest.raises(ValueError, match="contiguous"):
+        nf.nf_fold_dev(Fake(torch.uint8, 10, False), 10, 8)
+    ok = Fake(torch.uint8, 10)
+    ok.data_ptr = lambda: 0  # checked, never used: the next argument fails
+    with pytest.raises(ValueError, match="d_score"):
+        nf.nf_fold_dev(ok, 10, 8, d_score=Fake(torch.int64, 1))
+    with pytest.raises(ValueError, match="needs 100"):
+        nf.nf_fold_dev(ok, 10, 8, d_S=Fake(torch.int16, 99))
+    with pytest.raises(ValueError, match="int16"):
+        nf.nf_fold_dev(ok, 10, 8, d_S=Fake(torch.int32, 100))
+
+
+def test_allocator_hook_and_encode_are_host_calls(lib):
+    """nf_set_allocator takes both functions or neither; nf_encode maps
+    Section 2's alphabet to the codes nf_fold_dev takes, and rejects anything
+    else without writing."""
+    import numpy as np
+    from paper_1307_7820_amd import nf
+    A = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)(lambda n, c: None)
+    F = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)(lambda p, c: None)
+    a = ctypes.cast(A, ctypes.c_void_p)
+    f = ctypes.cast(F, ctypes.c_void_p)
+    assert lib.nf_set_allocator(a, None, None) == nf.NF_E_INVAL
+    assert lib.nf_set_allocator(None, f, None) == nf.NF_E_INVAL
+    assert lib.nf_set_allocator(a, f, None) == nf.NF_OK
+    assert lib.nf_set_allocator(None, None, None) == nf.NF_OK
+    nf.use_torch_allocator()  # the binding's default hook goes back in
+    assert list(nf.nf_encode("ACGUacgu")) == [0, 1, 2, 3, 0, 1, 2, 3]
+    assert nf.nf_encode("").size == 0
+    out = np.full(4, 7, dtype=np.uint8)
+    assert lib.nf_encode(b"ACTG", 4, out.ctypes.data) == nf.NF_E_INVAL
+    assert "base 2" in nf.last_error()
+    assert list(out) == [7, 7, 7, 7]
+    assert lib.nf_encode(b"A", nf.NF_MAX_N + 1, out.ctypes.data) == nf.NF_E_TOOLONG
+    with pytest.raises(nf.NFError):
+        nf.nf_encode("ACGN")
