@@ -148,6 +148,26 @@ int nf_fold_structure(const char* seq, int n, int q, char* db_out);
  * on different streams must be ordered by the caller. */
 int nf_fold_dev(const uint8_t* d_codes, int n, int q, int32_t* d_score, int16_t* d_S, void* stream);
 
+/* ---- Single fold on device buffers, allocating nothing ----
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, result and stream semantics as nf_fold_dev, and the same
+ * kernels, but every buffer beyond the caller's inputs and outputs (R, the
+ * padded codes, the dense table, the packed words, the accumulators, the
+ * work lists) lives in one static device array of NF_NOALLOC_SCRATCH_BYTES
+ * that each GPU the library runs on holds until the process ends.  The call
+ * makes kernel launches on `stream` only: no allocation, no host copy, no
+ * memset, so it can be captured into a graph.  It always runs the fused
+ * wavefront steps with R lookups (NF_MODE and NF_BETWEEN do not apply).
+ * A fold whose buffers do not fit the array (about n > 3200 at q = 8,
+ * n > 2900 at q = 4) is NF_E_NOMEM, with the bytes it needs in
+ * nf_last_error(), before any device work.  Every call on a GPU shares that
+ * GPU's array and overwrites what the last call left there: calls that
+ * overlap on one GPU (on different streams, or a graph replayed while
+ * another call runs) race, and the caller must order them. */
+#define NF_NOALLOC_SCRATCH_BYTES (32u << 20)
+int nf_fold_dev_noalloc(const uint8_t* d_codes, int n, int q, int32_t* d_score, int16_t* d_S, void* stream);
+
 /* ---- Batched folds: one packed wavefront over many sequences ----
  * A prepared batch uploads the codes of all sequences once, builds the packed
  * per-diagonal work lists of all of them and captures the whole fill as one

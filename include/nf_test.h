@@ -18,8 +18,11 @@ extern "C" {
  * A+1 < C < B-1, exactly once in the stage before its finish, in one
  * accumulator slot (combined atomically when split) that the finish then
  * reads; no two tiles of a stage sharing a slot; slot halves alternating by
- * stage.  Returns 0 when they hold, 1 with the first violation written to msg
- * (cap bytes, NUL-terminated), NF_E_INVAL for bad arguments. */
+ * stage.  For a single fold (count = 1) it also checks that the closed form
+ * of the schedule that the allocation-free entry point evaluates on the
+ * device gives the same items, in the same order and slots.  Returns 0 when
+ * they hold, 1 with the first violation written to msg (cap bytes,
+ * NUL-terminated), NF_E_INVAL for bad arguments. */
 int nf_test_schedule(const int* NTs, int count, int target, char* msg, int cap);
 
 #ifdef __cplusplus

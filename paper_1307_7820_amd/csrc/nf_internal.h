@@ -82,6 +82,65 @@ struct TileItem {
     int fold, A, d, slot0, nslot, pad0, pad1, pad2;
 };
 
+// The packed wavefront schedule of one fold alone, in closed form: the same
+// items, in the same order and slots, as the host's schedule builder makes
+// for a single fold of NT tiles per side at `target` between chunks per step
+// (a host test checks the two against each other).  Stage sg finishes the
+// tiles of diagonal sg and runs the between chunks of diagonal sg+1; the
+// between work of tile (A, A+d), d >= 4, is cut into chunks(d) pieces of its
+// group tiles C in [A+2, A+d-2], combined in accumulator slot
+// A + (stage parity) * max_slots.
+struct SingleSchedule {
+    int NT = 0, target = 1;
+
+    __host__ __device__ int max_slots() const { return NT >= 5 ? NT - 4 : 0; }
+    // chunks per tile of diagonal dd (0 when the diagonal has no between work)
+    __host__ __device__ int chunks(int dd) const
+    {
+        if (dd < 4 || NT <= dd) return 0;
+        const long long W = (long long)(NT - dd) * (dd - 3);
+        long long chunk = (W + target - 1) / target;
+        if (chunk < 1) chunk = 1;
+        return (int)((dd - 3 + chunk - 1) / chunk);
+    }
+    __host__ __device__ int finishes(int sg) const { return (sg >= 1 && sg < NT) ? NT - sg : 0; }
+    __host__ __device__ long long finish_offset(int sg) const
+    {
+        return sg <= 1 ? 0 : (long long)(sg - 1) * NT - (long long)(sg - 1) * sg / 2;
+    }
+    __host__ __device__ int between_count(int sg) const { return (NT - sg - 1) * chunks(sg + 1); }
+    __host__ __device__ long long between_offset(int sg) const
+    {
+        long long off = 0;
+        for (int s = 0; s < sg; ++s) off += between_count(s);
+        return off;
+    }
+    __host__ __device__ TileItem finish(int sg, int A) const
+    {
+        TileItem it{0, A, sg, 0, 0, 0, 0, 0};
+        if (sg >= 4) {
+            it.slot0 = A + ((sg - 1) & 1) * max_slots();
+            it.nslot = 1;
+        }
+        return it;
+    }
+    // item k of stage sg: tile A = k / ns, chunk k % ns
+    __host__ __device__ BetweenItem between(int sg, int k) const
+    {
+        const int dd = sg + 1, ns = chunks(dd), nC = dd - 3;
+        const int A = k / ns, c = k - A * ns;
+        BetweenItem it{};
+        it.fold = 0;
+        it.A = A;
+        it.d = dd;
+        it.c0 = A + 2 + (int)((long long)c * nC / ns);
+        it.c1 = A + 2 + (int)((long long)(c + 1) * nC / ns);
+        it.slot = A + (sg & 1) * max_slots();
+        it.pad0 = ns > 1 ? 1 : 0;
+        return it;
+    }
+};
+
 // Device-side work items: the fold's descriptor travels inside the item, so a
 // workgroup reaches its data with a single dependent load.
 // acc points at the tile's 64x64 int32 accumulator (between-group maxima).

@@ -158,6 +158,9 @@ int ensure_device()
     HIPCHK(hipGetDeviceProperties(&prop, dev));
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(NF_E_DEVICE, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+    // the static scratch of the allocation-free entry point; a failed lookup
+    // only disables that entry point, which reports it
+    if (scratch_setup(dev) != NF_OK) clear_error();
     c.device = dev;
     c.num_cu = prop.multiProcessorCount;
     HIPCHK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
@@ -932,6 +935,43 @@ std::string check_schedule(const std::vector<int>& NTs, int target)
     return "";
 }
 
+// The closed form SingleSchedule, which the allocation-free entry point
+// evaluates on the device, against build_schedule for one fold: the same
+// items in the same order, and the same slot count.
+std::string check_single_schedule(int NT, int target)
+{
+    Schedule sc;
+    build_schedule({NT}, target, sc);
+    SingleSchedule S;
+    S.NT = NT;
+    S.target = target;
+    char buf[256];
+    auto bad = [&](const char* what, int sg, long long k) {
+        snprintf(buf, sizeof buf, "single schedule NT %d target %d: %s at stage %d item %lld", NT, target, what, sg, k);
+        return std::string(buf);
+    };
+    if (sc.max_slots != S.max_slots()) return bad("max_slots", -1, sc.max_slots);
+    if ((int)sc.diag.size() != NT) return bad("diagonal count", 0, (long long)sc.diag.size());
+    for (int sg = 0; sg < sc.stages; ++sg) {
+        if (sc.tile_cnt[sg] != S.finishes(sg)) return bad("finish count", sg, sc.tile_cnt[sg]);
+        if (sg >= 1 && sc.tile_off[sg] != S.finish_offset(sg)) return bad("finish offset", sg, sc.tile_off[sg]);
+        for (int A = 0; A < sc.tile_cnt[sg]; ++A) {
+            const TileItem a = sc.tile[sc.tile_off[sg] + A], b = S.finish(sg, A);
+            if (a.fold != b.fold || a.A != b.A || a.d != b.d || a.nslot != b.nslot || (a.nslot && a.slot0 != b.slot0))
+                return bad("finish item", sg, A);
+        }
+        if (sc.btw_cnt[sg] != S.between_count(sg)) return bad("between count", sg, sc.btw_cnt[sg]);
+        if (sc.btw_off[sg] != S.between_offset(sg)) return bad("between offset", sg, sc.btw_off[sg]);
+        for (int k = 0; k < sc.btw_cnt[sg]; ++k) {
+            const BetweenItem a = sc.btw[sc.btw_off[sg] + k], b = S.between(sg, k);
+            if (a.fold != b.fold || a.A != b.A || a.d != b.d || a.c0 != b.c0 || a.c1 != b.c1 || a.slot != b.slot ||
+                a.pad0 != b.pad0)
+                return bad("between item", sg, k);
+        }
+    }
+    return "";
+}
+
 }  // namespace
 }  // namespace nf
 
@@ -942,7 +982,8 @@ extern "C" int nf_test_schedule(const int* NTs, int count, int target, char* msg
     std::vector<int> v(NTs, NTs + count);
     for (int x : v)
         if (x < 1) return NF_E_INVAL;
-    const std::string err = nf::check_schedule(v, target);
+    std::string err = nf::check_schedule(v, target);
+    if (err.empty() && count == 1) err = nf::check_single_schedule(v[0], target);
     if (msg && cap > 0) snprintf(msg, (size_t)cap, "%s", err.c_str());
     return err.empty() ? NF_OK : 1;
 }

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <memory>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -135,6 +136,10 @@ struct Context {
 
 Context& ctx();
 int ensure_device();
+std::recursive_mutex& api_mutex();  // serialises the host entry points
+// Device address of the allocation-free entry point's static scratch array,
+// looked up once per device at set-up (nf_noalloc.hip).
+int scratch_setup(int device);
 int get_R(int q, const uint8_t** out);
 int encode_sequence(const char* seq, int n, uint8_t* out);
 int check_length(int n);

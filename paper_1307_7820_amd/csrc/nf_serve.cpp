@@ -29,8 +29,6 @@
 
 namespace nf {
 
-std::recursive_mutex& api_mutex();
-
 namespace {
 
 using Clock = std::chrono::steady_clock;

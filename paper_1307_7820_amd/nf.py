@@ -43,7 +43,7 @@ _CODE_NAMES = {
 EXPORTS = [
     "nf_last_error", "nf_init", "nf_shutdown", "nf_set_allocator", "nf_encode",
     "nf_precompute_R", "nf_copy_R", "nf_fold", "nf_fold_structure",
-    "nf_fold_dev", "nf_batch_create", "nf_batch_run", "nf_batch_scores", "nf_batch_table",
+    "nf_fold_dev", "nf_fold_dev_noalloc", "nf_batch_create", "nf_batch_run", "nf_batch_scores", "nf_batch_table",
     "nf_batch_info", "nf_batch_structures", "nf_batch_destroy", "nf_fold_batch", "nf_serve_config", "nf_fold_bytes",
     "nf_submit", "nf_poll", "nf_wait", "nf_poll_ex", "nf_serve_stats", "nf_autotune_q",
     "nf_autotune_target", "nf_autotune", "nf_profile_fold",
@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "nf_fold": (c_int, [ctypes.c_char_p, c_int, c_int, vp]),
         "nf_fold_structure": (c_int, [ctypes.c_char_p, c_int, c_int, vp]),
         "nf_fold_dev": (c_int, [vp, c_int, c_int, vp, vp, vp]),
+        "nf_fold_dev_noalloc": (c_int, [vp, c_int, c_int, vp, vp, vp]),
         "nf_batch_create": (c_int, [vp, vp, c_int, c_int, ctypes.POINTER(vp)]),
         "nf_batch_run": (c_int, [vp, vp]),
         "nf_batch_scores": (c_int, [vp, vp]),
@@ -301,6 +302,18 @@ def nf_fold_dev(d_codes, n: int, q: int = 0, d_score=None, d_S=None, stream=None
     ps = _dev_ptr(d_score, "int32", 1, "d_score")
     pS = _dev_ptr(d_S, "int16", n * n, "d_S")
     _check(load().nf_fold_dev(pc, n, q, ps, pS, _stream_handle(stream)))
+
+
+def nf_fold_dev_noalloc(d_codes, n: int, q: int = 0, d_score=None, d_S=None, stream=None) -> None:
+    """nf_fold_dev that allocates nothing: every buffer beyond the arguments
+    lives in the library's static device scratch (n up to about 3200 at
+    q = 8).  Same argument checks as nf_fold_dev."""
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    pc = _dev_ptr(d_codes, "uint8", n, "d_codes")
+    ps = _dev_ptr(d_score, "int32", 1, "d_score")
+    pS = _dev_ptr(d_S, "int16", n * n, "d_S")
+    _check(load().nf_fold_dev_noalloc(pc, n, q, ps, pS, _stream_handle(stream)))
 
 
 def nf_encode(seq) -> np.ndarray:

@@ -271,3 +271,24 @@ def test_allocator_hook_and_encode_are_host_calls(lib):
     assert lib.nf_encode(b"A", nf.NF_MAX_N + 1, out.ctypes.data) == nf.NF_E_TOOLONG
     with pytest.raises(nf.NFError):
         nf.nf_encode("ACGN")
+
+
+def test_noalloc_schedule_closed_form_and_size_limit(lib):
+    """The allocation-free entry point builds its work lists on the device
+    from a closed form of the single-fold schedule: the schedule hook checks
+    that form against the host's builder item by item.  Folds too large for
+    its static scratch are refused on the host, before any device call."""
+    from paper_1307_7820_amd import nf
+    msg = ctypes.create_string_buffer(256)
+    for NT in list(range(1, 70)) + [120, 251, 1024]:
+        for target in (1, 7, 256, 1024, 4096):
+            arr = (ctypes.c_int * 1)(NT)
+            rc = lib.nf_test_schedule(arr, 1, target, msg, 256)
+            assert rc == 0, (NT, target, msg.value)
+    rc = lib.nf_fold_dev_noalloc(1, 3264, 8, None, None, None)
+    assert rc == nf.NF_E_NOMEM and "scratch" in nf.last_error()
+    assert lib.nf_fold_dev_noalloc(1, 2944, 4, None, None, None) == nf.NF_E_NOMEM
+    # within the limit the call gets as far as the device, which is absent here
+    assert lib.nf_fold_dev_noalloc(1, 3263, 8, None, None, None) == nf.NF_E_DEVICE
+    assert lib.nf_fold_dev_noalloc(None, 10, 8, None, None, None) == nf.NF_E_INVAL
+    assert lib.nf_fold_dev_noalloc(1, 10, 10, None, None, None) == nf.NF_E_INVAL
