@@ -45,6 +45,27 @@ def command(out: str = LIB):
     return [HIPCC, *FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
 
 
+# The paper's serial CPU algorithms (include/nf_serial.h): plain host C++,
+# a library of its own that libnf.so never calls.
+SERIAL_LIB = os.path.join(HERE, "libnf_serial.so")
+SERIAL_FLAGS = ["-O3", "-march=x86-64-v3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-Wall", "-I" + INCLUDE]
+
+
+def serial_command(out: str = SERIAL_LIB):
+    return [os.environ.get("CXX", "g++"), *SERIAL_FLAGS, os.path.join(CSRC, "nf_serial.cpp"), "-o", out]
+
+
+def build_serial(verbose: bool = False) -> str:
+    """Compile nf_serial.cpp into libnf_serial.so (always recompiles)."""
+    tmp = SERIAL_LIB + ".tmp%d" % os.getpid()
+    cmd = serial_command(tmp)
+    if verbose:
+        print(" ".join(shlex.quote(c) for c in cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, SERIAL_LIB)
+    return SERIAL_LIB
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source into libnf.so (always recompiles)."""
     tmp = LIB + ".tmp%d" % os.getpid()
@@ -67,5 +88,7 @@ def up_to_date() -> bool:
 if __name__ == "__main__":
     if "--print" in sys.argv:
         print(" ".join(shlex.quote(c) for c in command()))
+        print(" ".join(shlex.quote(c) for c in serial_command()))
     else:
         print(build(verbose=True))
+        print(build_serial(verbose=True))
