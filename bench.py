@@ -34,8 +34,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: int32 VALU lane-ops/s
-OPS_PER_LOOKUP = 2.5                          # index add + 3-input add + half a 3-input max
+OPS_PER_LOOKUP = 3.0                          # Eq. 3 lookup: form the R index, add the two bases and R, max
 OPS_PER_TERM = 2.0                            # add + max of one Eq. 1 term
+# algorithmic HBM bytes of a lookup when the packed words (int16 base + 8-bit
+# difference vector, one per row and one per column of a group) are reused
+# over a 64 x 64-cell tile: 2 x 3 bytes per 64 lookups
+HBM_BYTES_PER_LOOKUP = 6.0 / 64
 TUNE_REPS = 5                                 # folds per candidate when the headline q and chunk target are tuned
 PEAK_HBM = 8.0e12
 
@@ -118,37 +122,127 @@ def traffic_bytes(kernel: str, q: int, n: int, target: int):
         return None
 
 
-def roofline(nf, codes, n, q, reps=3):
+def lds_ceiling(nf, q: int):
+    """Measured LDS 1-byte gather rates over a table of R's size for q:
+    offsets uniform over the table, and one wave-uniform row of R with a
+    random column per lane (the pattern of the between-group lookups)."""
+    table = max(64, 1 << (2 * (q - 1)))
+    row = 1 << (q - 1)
+    uniform = nf.nf_lds_gather_rate(table, 0)
+    rowwise = nf.nf_lds_gather_rate(table, row if table % row == 0 and row <= table else 0)
+    return {"table_bytes": table, "row_bytes": row, "uniform_gathers_per_s": uniform, "row_gathers_per_s": rowwise}
+
+
+def roofline_times(lookups: float, terms: float, cells_out: float, seconds: float, lds_rate: float):
+    """t* = max(t_VALU, t_LDS, t_HBM) for the given algorithmic work, and the
+    roofline object with the binding unit's achieved and peak rates (so that
+    frac = achieved / peak = t* / t)."""
+    t_valu = (OPS_PER_LOOKUP * lookups + OPS_PER_TERM * terms) / PEAK_VALU_LANE_OPS
+    t_lds = lookups / lds_rate
+    hbm_bytes = HBM_BYTES_PER_LOOKUP * lookups + 2.0 * cells_out
+    t_hbm = hbm_bytes / PEAK_HBM
+    t_star = max(t_valu, t_lds, t_hbm)
+    if t_star == t_valu:
+        out = {"bound": "alu", "achieved": (OPS_PER_LOOKUP * lookups + OPS_PER_TERM * terms) / seconds / 1e12,
+               "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "TOP/s"}
+    elif t_star == t_lds:
+        out = {"bound": "lds", "achieved": lookups / seconds / 1e9, "peak": lds_rate / 1e9, "unit": "Ggathers/s"}
+    else:
+        out = {"bound": "hbm", "achieved": hbm_bytes / seconds / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    out["frac"] = out["achieved"] / out["peak"]
+    out["t_valu_us"], out["t_lds_us"], out["t_hbm_us"], out["t_us"] = (1e6 * t_valu, 1e6 * t_lds, 1e6 * t_hbm,
+                                                                      1e6 * seconds)
+    out["algorithmic_hbm_bytes"] = hbm_bytes
+    return out
+
+
+def roofline(nf, codes, n, q, lds, reps=3):
     """Roofline of the kernel that takes most of the fill's device time.
 
-    Algorithmic work per launch = 2.5 VALU lane-ops per Eq. 3 lookup + 2 per
-    Eq. 1 term evaluated one by one inside a tile (add, max), both counted
-    from the work lists; duration = the kernel's own start and end, recorded
-    into HIP events by its dispatch on the launching stream."""
+    Algorithmic work per launch, from the work lists (nf_profile_fold):
+    3 VALU lane-ops per Eq. 3 lookup and 2 per Eq. 1 term evaluated one by
+    one, one LDS byte gather per lookup, and 6/64 HBM bytes per lookup plus
+    2 bytes per table cell written.  Duration = the kernel's own start and
+    end, recorded into HIP events by its dispatch on the launching stream.
+    The LDS rate is the measured row-pattern gather ceiling."""
     prof = nf.nf_profile_fold(codes, n, q, reps)
     target = nf.nf_autotune_target(n, q)  # the chunks per step the profiled plan was built with
     ks = [i for i in range(len(nf.KERNEL_NAMES)) if prof.launches[i] > 0]
     k = max(ks, key=lambda i: prof.ms[i])
     name = nf.KERNEL_NAMES[k]
     per_launch_s = prof.ms[k] / 1e3 / prof.launches[k]
-    ops = (OPS_PER_LOOKUP * prof.lookups[k] + OPS_PER_TERM * prof.splits[k]) / prof.launches[k]
-    ach = ops / per_launch_s / 1e12
-    peak = PEAK_VALU_LANE_OPS / 1e12
+    L = prof.lookups[k] / prof.launches[k]
+    X = prof.splits[k] / prof.launches[k]
+    C = prof.cells[k] / prof.launches[k]
+    r = roofline_times(L, X, C, per_launch_s, lds["row_gathers_per_s"])
+    traffic = traffic_bytes(name, q, n, target)
     out = {"kernel": name, "launches_per_fold": prof.launches[k] // reps,
            "avg_launch_us": 1e6 * per_launch_s,
            "per_kernel_ms_per_fold": {nf.KERNEL_NAMES[i]: prof.ms[i] / reps for i in ks},
-           "bound": "alu", "achieved": ach, "peak": peak, "unit": "TOP/s", "frac": ach / peak,
-           "lookups_per_launch": prof.lookups[k] / prof.launches[k],
-           "terms_per_launch": prof.splits[k] / prof.launches[k],
+           **r,
+           "lookups_per_launch": L, "terms_per_launch": X, "cells_per_launch": C,
            "glookups_per_s": prof.lookups[k] / (prof.ms[k] / 1e3) / 1e9,
-           "traffic": traffic_bytes(name, q, n, target),
-           "q": prof.q, "tile": prof.tile, "between_chunks_per_step": target}
+           "traffic": traffic,
+           "hbm_achieved_gbs": traffic / per_launch_s / 1e9 if traffic else None,
+           "hbm_frac": traffic / per_launch_s / PEAK_HBM if traffic else None,
+           "q": prof.q, "tile": prof.tile, "between_chunks_per_step": target,
+           "fold": {"lookups": sum(prof.lookups[i] for i in ks) / reps,
+                    "terms": sum(prof.splits[i] for i in ks) / reps}}
     return out
 
 
-def cpu_baseline(seq: str, budget_s: float):
+def fold_work(n: int, q: int):
+    """Algorithmic work of one fill, counted as the kernels run it (the same
+    counts nf_profile_fold reports per launch, summed): Eq. 3 lookups, Eq. 1
+    terms evaluated one by one, and table cells written."""
+    G = 64 // q
+    T = G * q
+    NT = -(-(n + 1) // T)
+
+    def valid(B):
+        return max(0, min(T, n + 1 - B * T))
+    lookups = terms = cells_out = 0.0
+    for B in range(NT):
+        v = valid(B)
+        # main-diagonal tile: cell (i, i+t) has t-1 split points and a pairing term
+        terms += sum((v - t) * t for t in range(1, v))
+        cells_out += v * (v + 1) / 2
+        if B == 0:
+            continue
+        between = (B - 3) * (B - 2) / 2 if B >= 4 else 0          # sum over d = 4..B of d - 3
+        ends = 2 * B - 3 if B >= 2 else 0                         # sum over d = 1..B of min(d - 1, 2)
+        lookups += (between + ends) * G * T * v
+        own_rows = v * 8 * 28 if 8 % q == 0 else v * T * (T - 1) / 2
+        block = v * 8 * 28 * (8 // q) if 8 % q == 0 else 0
+        lookups += B * block
+        terms += B * (T * v * (v - 1) / 2 + own_rows + T * v)
+        cells_out += B * T * v
+    return lookups, terms, cells_out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(seq: str, gen, budget_s: float):
+    """The CPU oracle (plain Eq. 1, OpenMP over the cells of a diagonal) on
+    this host, as it stands.  Headline value: whole n = 6000 folds on all the
+    threads OpenMP gives it.  Beside it: one thread (a bounded sample, the
+    first 3000 bases, scaled to n = 6000 by the split count, since its time
+    is proportional to (n-1)n(n+1)/6), and the batch workload (512 of the 4096
+    sequences, one thread each on as many workers as the oracle's threads)."""
     import oracle
+    from concurrent.futures import ThreadPoolExecutor
     threads = oracle.threads_used()
+    n = len(seq)
     t0 = time.perf_counter()
     reps = 0
     score = None
@@ -156,18 +250,36 @@ def cpu_baseline(seq: str, budget_s: float):
         score = oracle.fold_score(seq)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or el / reps * (reps + 1) > 3 * budget_s:
+        if el >= budget_s or el / reps * (reps + 1) > 2 * budget_s:
             break
     per = el / reps
-    return {"value": cells(len(seq)) / per / 1e9, "unit": "GCUPS", "cores": threads, "kind": "oracle",
-            "sample": "%d full fold(s) of the same n=%d sequence, %.2f s each" % (reps, len(seq), per)}, score
+    sub = seq[:3000]
+    t0 = time.perf_counter()
+    oracle.fold_score(sub, nthreads=1)
+    one = time.perf_counter() - t0
+    one_scaled = one * splits(n) / splits(len(sub))
+    seqs = gen.workload_batch4096()[::8]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda x: oracle.fold_score(x, nthreads=1), seqs))
+    bt = time.perf_counter() - t0
+    out = {"value": cells(n) / per / 1e9, "unit": "GCUPS", "cores": threads, "kind": "oracle",
+           "sample": "%d full fold(s) of the n=%d sequence on %d OpenMP threads, %.2f s each" % (reps, n, threads, per),
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "single_thread": {"value": cells(n) / one_scaled / 1e9, "unit": "GCUPS", "cores": 1,
+                             "sample": "one fold of the first %d bases, %.2f s, scaled by split count to n=%d (%.1f s)"
+                                       % (len(sub), one, n, one_scaled)},
+           "batch4096": {"value": len(seqs) / bt, "unit": "folds/s", "cores": threads,
+                         "sample": "%d of the 4096 batch sequences (every 8th), one thread each on %d workers, %.2f s"
+                                   % (len(seqs), threads, bt)}}
+    return out, score
 
 
-def extra_n16000(nf, torch, gen, steps):
+def extra_n16000(nf, torch, gen, steps, lds):
     seq = gen.workload_n16000()
     ms, wall, score, codes = time_fold(nf, torch, seq, 8, steps, 1)
     t = ms / 1e3 / steps
-    r = roofline(nf, codes, len(seq), 8, reps=1)
+    r = roofline(nf, codes, len(seq), 8, lds, reps=1)
     return {"n": 16000, "q": 8, "ms_per_fold": t * 1e3, "gcups": cells(16000) / t / 1e9,
             "split_equivalent_gsps": splits(16000) / t / 1e9,
             "glookups_per_s": r.get("glookups_per_s"), "score": score, "roofline": r}
@@ -242,7 +354,11 @@ def extra_structure(nf, gen, reps=3):
     return out
 
 
-def extra_batch(nf, torch, gen, looped_sample: int):
+def extra_batch(nf, torch, gen, lds):
+    """The 4096-sequence batch: one prepared batch (one HIP graph) against the
+    same 4096 folds run one by one with the single-fold call (device codes,
+    every plan made and captured before the timed loop), both timed over all
+    4096 folds."""
     seqs = gen.workload_batch4096()
     t0 = time.perf_counter()
     b = nf.Batch(seqs, q=8)
@@ -267,28 +383,28 @@ def extra_batch(nf, torch, gen, looped_sample: int):
     dbs = b.structures()
     structures_ms = (time.perf_counter() - t0) * 1e3
     b.close()
-    # looped single-fold kernel on a sample of the same sequences (device codes,
-    # plans warmed first), extrapolated to all 4096
-    idx = list(range(0, len(seqs), max(1, len(seqs) // looped_sample)))[:looped_sample]
-    cds = [torch.from_numpy(nf.encode(seqs[i])).cuda() for i in idx]
-    d_score = torch.zeros(1, dtype=torch.int32, device="cuda")
-    for i, c in zip(idx, cds):
-        nf.nf_fold_dev(c, len(seqs[i]), 8, d_score, None, stream)
+    # the same folds looped one by one
+    cds = [torch.from_numpy(nf.encode(s)).cuda() for s in seqs]
+    d_scores = torch.zeros(len(seqs), dtype=torch.int32, device="cuda")
+    for i, c in enumerate(cds):  # makes and captures every single-fold plan
+        nf.nf_fold_dev(c, len(seqs[i]), 8, d_scores[i:i + 1], None, stream)
     torch.cuda.synchronize()
     e0.record(stream)
-    for i, c in zip(idx, cds):
-        nf.nf_fold_dev(c, len(seqs[i]), 8, d_score, None, stream)
+    for i, c in enumerate(cds):
+        nf.nf_fold_dev(c, len(seqs[i]), 8, d_scores[i:i + 1], None, stream)
     e1.record(stream)
     torch.cuda.synchronize()
     loop_ms = e0.elapsed_time(e1)
-    frac = sum(len(seqs[i]) ** 3 for i in idx) / sum(len(s) ** 3 for s in seqs)
-    looped_est_ms = loop_ms / frac
+    looped_same = bool(torch.equal(d_scores.cpu(), torch.from_numpy(scores)))
     tot_cells = sum(cells(len(s)) for s in seqs)
+    work = [fold_work(len(s), 8) for s in seqs]
+    roof = roofline_times(sum(w[0] for w in work), sum(w[1] for w in work), sum(w[2] for w in work), ms / 1e3,
+                          lds["row_gathers_per_s"])
     return {"count": len(seqs), "ms_per_batch": ms, "folds_per_s": len(seqs) / (ms / 1e3),
             "gcups": tot_cells / (ms / 1e3) / 1e9, "prepare_s": prep,
-            "looped_sample": len(idx), "looped_ms_sample": loop_ms,
-            "looped_est_ms_all": looped_est_ms, "looped_folds_per_s": len(seqs) / (looped_est_ms / 1e3),
-            "speedup_vs_looped": looped_est_ms / ms, "score_checksum": int(scores.sum()),
+            "looped_ms_all": loop_ms, "looped_folds_per_s": len(seqs) / (loop_ms / 1e3),
+            "speedup_vs_looped": loop_ms / ms, "looped_scores_equal_batch": looped_same,
+            "roofline_whole_fill": roof, "score_checksum": int(scores.sum()),
             "structures_ms": structures_ms, "structure_pairs": sum(db.count("(") for db in dbs)}
 
 
@@ -297,13 +413,15 @@ def _pct(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if xs else None
 
 
-def extra_serving(nf, torch, gen, count=600, warm=60, budget=2 << 30):
+def extra_serving(nf, torch, gen, count=2000, warm=200, budget=2 << 30):
     """FIFO single folds (plain) vs the continuous-batching engine (served).
 
     Same request sequence for both (lengths 80% U{100..500}, 20% U{2000..8000},
-    iid bases).  Saturation: every request available at t=0.  Open loop:
-    Poisson arrivals at 0.8 x the plain saturation rate; latency = completion
-    observed by the caller - arrival.
+    iid bases): `warm` requests to warm up, then `count` measured ones.
+    Saturation: every request available at t=0.  Open loop: Poisson arrivals
+    at 0.8 x the plain saturation rate; latency = completion observed by the
+    caller - arrival.  budget = device bytes the active folds may hold (0: 80%
+    of the free device memory when the engine starts).
     """
     import threading
     import numpy as np
@@ -328,6 +446,7 @@ def extra_serving(nf, torch, gen, count=600, warm=60, budget=2 << 30):
     mu_plain = count / plain_T
 
     nf.nf_shutdown()
+    torch.cuda.empty_cache()  # a budget of 0 reads the device's free memory
     nf.nf_serve_config(budget, 256, 0)
 
     def served_run(arrivals):
@@ -386,8 +505,10 @@ def extra_serving(nf, torch, gen, count=600, warm=60, budget=2 << 30):
     lat_served = [done_t[k] - arrivals[k] for k in range(count)]
     st = nf.nf_serve_stats()
     nf.nf_shutdown()
+    torch.cuda.empty_cache()
     return {
-        "requests": count, "budget_bytes": budget, "mean_n": float(np.mean([len(seqs[i]) for i in meas])),
+        "requests": count, "warmup_requests": warm, "budget_bytes": int(st.budget_bytes),
+        "mean_n": float(np.mean([len(seqs[i]) for i in meas])),
         "saturation_folds_per_s": {"plain_fifo": mu_plain, "served": mu_served},
         "open_loop_rate_per_s": lam,
         "latency_ms_plain": {"p50": 1e3 * _pct(lat_plain, 50), "p99": 1e3 * _pct(lat_plain, 99)},
@@ -395,6 +516,31 @@ def extra_serving(nf, torch, gen, count=600, warm=60, budget=2 << 30):
         "served_over_plain_throughput": mu_served / mu_plain,
         "engine_steps": int(st.steps), "engine_steps_fused": int(st.steps_fused), "peak_bytes": int(st.peak_bytes),
     }
+
+
+def extra_serial(gen):
+    """The paper's serial CPU algorithms (Section 3; libnf_serial.so) on this
+    host, one thread, at two of the lengths of the paper's serial table, with
+    the plain recurrence they are compared against; and the two-vector method
+    on every thread (diagonal order).  Context for the paper's ratios."""
+    from paper_1307_7820_amd import serial
+    out = {"cpu_model": cpu_model()}
+    for n in (2000, 4000):
+        seq = gen.iid_sequence(n, [1307, 2])
+        row = {}
+        for label, q, variant, threads in (("plain", 1, "plain", 1), ("two_vector_q8", 8, "two_vector", 1),
+                                           ("partial_memo_q8", 8, "partial_memo", 1),
+                                           ("full_memo_q8", 8, "full_memo", 1), ("fg_q3", 3, "fg", 1),
+                                           ("two_vector_q8_all_threads", 8, "two_vector", os.cpu_count() or 1)):
+            t0 = time.perf_counter()
+            score, st = serial.nf_serial_fold(seq, q, variant, threads)
+            row[label] = {"s": time.perf_counter() - t0, "score": score, "threads": threads,
+                          "lookups": st.lookups, "r_entries": st.r_entries}
+        for k in list(row):
+            if k != "plain":
+                row[k]["speedup_over_plain"] = row["plain"]["s"] / row[k]["s"]
+        out["n%d" % n] = row
+    return out
 
 
 def run_only(args, torch, gen, nf):
@@ -410,6 +556,9 @@ def run_only(args, torch, gen, nf):
         print(json.dumps({"only": "copy", "bytes_per_copy": x.numel(), "copies": args.warmup + args.steps}))
         return
     nf.nf_init(0)
+    if args.only == "ldsgather":
+        print(json.dumps({"only": "ldsgather", **{"q%d" % q: lds_ceiling(nf, q) for q in (4, 6, 8, 9)}}))
+        return
     if args.only == "serving":
         # the serving extra alone (plain FIFO, saturation, open loop)
         print(json.dumps({"only": "serving", **extra_serving(nf, torch, gen)}))
@@ -452,7 +601,7 @@ def main():
     ap.add_argument("--cpu-budget-s", type=float, default=10.0)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra workloads)")
     ap.add_argument("--only", choices=["n6000", "n16000", "batch", "copy", "structure6000", "structure16000",
-                                       "plain16000", "serving"],
+                                       "plain16000", "serving", "ldsgather"],
                     help="run one workload K times and print a short line (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -484,9 +633,16 @@ def main():
     ms_per = ms / args.steps
     value = cells(n) * args.steps / (ms / 1e3) / 1e9
     log("bench: %.3f ms/fold, %.2f GCUPS, score %d" % (ms_per, value, score))
-    roof = roofline(nf, codes, n, q)
+    lds = lds_ceiling(nf, q)
+    log("bench: lds gather ceiling %s" % json.dumps(lds))
+    roof = roofline(nf, codes, n, q, lds)
     log("bench: roofline %s" % json.dumps(roof))
-    cpu, cpu_score = cpu_baseline(seq, args.cpu_budget_s)
+    fw = fold_work(n, q)
+    if abs(fw[0] - roof["fold"]["lookups"]) > 1e-6 * fw[0] or abs(fw[1] - roof["fold"]["terms"]) > 1e-6 * fw[1]:
+        log("bench: work count mismatch: %s vs %s" % (fw, roof["fold"]))
+        sys.exit(1)
+    fold_roof = roofline_times(fw[0], fw[1], fw[2], ms_per / 1e3, lds["row_gathers_per_s"])
+    cpu, cpu_score = cpu_baseline(seq, gen, args.cpu_budget_s)
     log("bench: cpu baseline %s" % json.dumps(cpu))
     if cpu_score != score:
         log("bench: SCORE MISMATCH gpu %d vs oracle %d" % (score, cpu_score))
@@ -494,12 +650,12 @@ def main():
     extra = {}
     if not args.quick:
         try:
-            extra["n16000"] = extra_n16000(nf, torch, gen, 3)
+            extra["n16000"] = extra_n16000(nf, torch, gen, 3, lds)
             log("bench: n16000 %s" % json.dumps(extra["n16000"]))
         except Exception as e:  # reported, never hidden
             extra["n16000"] = {"error": repr(e)}
         try:
-            extra["batch4096"] = extra_batch(nf, torch, gen, 256)
+            extra["batch4096"] = extra_batch(nf, torch, gen, lds)
             log("bench: batch %s" % json.dumps(extra["batch4096"]))
         except Exception as e:
             extra["batch4096"] = {"error": repr(e)}
@@ -518,11 +674,17 @@ def main():
             log("bench: structure %s" % json.dumps(extra["structure"]))
         except Exception as e:
             extra["structure"] = {"error": repr(e)}
+        for label, budget in (("serving_2GiB", 2 << 30), ("serving_free_hbm", 0)):
+            try:
+                extra[label] = extra_serving(nf, torch, gen, budget=budget)
+                log("bench: %s %s" % (label, json.dumps(extra[label])))
+            except Exception as e:
+                extra[label] = {"error": repr(e)}
         try:
-            extra["serving"] = extra_serving(nf, torch, gen)
-            log("bench: serving %s" % json.dumps(extra["serving"]))
+            extra["serial_cpu"] = extra_serial(gen)
+            log("bench: serial %s" % json.dumps(extra["serial_cpu"]))
         except Exception as e:
-            extra["serving"] = {"error": repr(e)}
+            extra["serial_cpu"] = {"error": repr(e)}
     line = {
         "metric": "Nussinov GCUPS at n=6000/16000; batched folds/s + p99 latency vs plain",
         "value": value, "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -534,6 +696,8 @@ def main():
                    "tile": roof.get("tile"), "score": score},
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": roof,
+        "roofline_whole_fold": fold_roof,
+        "lds_gather_ceiling": lds,
         "cpu_baseline": cpu,
         "extra": extra,
     }

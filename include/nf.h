@@ -302,9 +302,12 @@ int nf_autotune(int n, int qmin, int qmax, int reps);
  * diagonal and the between-group chunks of the next); the fill runs in the
  * execution its workspace uses (see nf_fold).  For every class:
  * lookups[k] counts the Four-Russians steps of Eq. 3 on table cells (padding
- * excluded), splits[k] the terms of Eq. 1 evaluated one by one inside tiles
- * (split points within a tile's own rows or columns, plus the pairing term),
- * cells[k] the table cells finished.  Synchronous. */
+ * excluded): the groups between the end tiles, those of the two end tiles,
+ * and, when q divides 8, the groups of each finished 8-row block of a tile
+ * for the rows above it; splits[k] the terms of Eq. 1 evaluated one by one
+ * (split points within a tile's own columns, those within its own rows that
+ * are not looked up, plus the pairing term); cells[k] the table cells
+ * finished.  Synchronous. */
 typedef struct {
     int64_t launches[4];
     double ms[4];
@@ -314,6 +317,17 @@ typedef struct {
     int q, tile, tiles_per_side, stages;
 } nf_kernel_profile_t;
 int nf_profile_fold(const uint8_t* d_codes, int n, int q, int reps, void* stream, nf_kernel_profile_t* out);
+
+/* The device's LDS byte-gather ceiling, the second unit a lookup of Eq. 3
+ * uses besides VALU issue (one 1-byte read of R from LDS per lookup): every
+ * lane of 8 workgroups per CU repeatedly reads 16 fixed offsets of a
+ * table_bytes table in LDS with 1-byte loads.  row_bytes = 0 draws the
+ * offsets uniformly over the table; row_bytes > 0 gives each load of a
+ * wavefront one row of row_bytes bytes with a random byte per lane, the
+ * pattern of R[h][c] with a wave-uniform h (row_bytes = 2^(q-1)).  Writes
+ * lane-gathers per second.  table_bytes: a power of two in 64..65536;
+ * row_bytes: 0 or a divisor of it.  Synchronous. */
+int nf_lds_gather_rate(int table_bytes, int row_bytes, double* lane_gathers_per_s);
 
 #ifdef __cplusplus
 }

@@ -19,8 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnf.so")
 
-SOURCES = ["nf_kernels.hip", "nf_traceback.hip", "nf_plain.hip", "nf_noalloc.hip", "nf_runtime.cpp", "nf_api.cpp",
-           "nf_serve.cpp"]
+SOURCES = ["nf_kernels.hip", "nf_traceback.hip", "nf_plain.hip", "nf_noalloc.hip", "nf_measure.hip", "nf_runtime.cpp",
+           "nf_api.cpp", "nf_serve.cpp"]
 HEADERS = ["nf_internal.h", "nf_runtime.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -513,12 +513,23 @@ int plan_enqueue_direct(Plan& p, hipStream_t s)
 // Valid (non-padding) columns of tile column B of a fold.
 static int valid_cols(const Geom& g, int T, int B) { return std::max(0, std::min(T, g.n + 1 - B * T)); }
 
-// Terms of Eq. 1 evaluated one by one inside an off-diagonal tile with vb
-// valid columns: for cell (i, j) the split points in the tile's own rows
-// (T-1-i of them) and columns (j), plus the pairing term.
-static double tile_terms(int T, int vb)
+// Work of the finish of an off-diagonal tile with vb valid columns, as the
+// finish runs it.  Split points inside the tile's own columns (tile B): j for
+// cell (i, j), one by one in the row closure.  Split points inside its own
+// rows (tile A): when q divides 8 the rows are finished in 8-row blocks, a
+// row goes into the rows above it in its block one split at a time, and each
+// finished block's q-groups reach every row above the block by one lookup
+// (Eq. 3); otherwise every row goes into every row above it one split at a
+// time.  Plus the pairing term of every cell.
+static double tile_terms(int q, int T, int vb)
 {
-    return (double)vb * T * (T - 1) / 2 + (double)T * vb * (vb - 1) / 2 + (double)T * vb;
+    const double own_cols = (double)T * vb * (vb - 1) / 2;
+    const double own_rows = (8 % q == 0) ? (double)vb * 8 * 28 : (double)vb * T * (T - 1) / 2;
+    return own_cols + own_rows + (double)T * vb;
+}
+static double tile_block_lookups(int q, int vb)
+{
+    return (8 % q == 0) ? (double)vb * 8 * 28 * (8 / q) : 0.0;  // 8 rows x groups of the blocks below
 }
 // The same for a main-diagonal tile of v valid posts: cell (i, i+t) has t-1
 // split points and one pairing term (t >= 1).
@@ -544,8 +555,8 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
         for (int k = 0; k < sc.tile_cnt[sg]; ++k) {
             const TileItem& it = sc.tile[sc.tile_off[sg] + k];
             const int vb = valid_cols(p.geom[it.fold], T, it.A + it.d);
-            tile_lk[sg] += (double)std::min(std::max(it.d - 1, 0), 2) * G * T * vb;
-            tile_sp[sg] += tile_terms(T, vb);
+            tile_lk[sg] += (double)std::min(std::max(it.d - 1, 0), 2) * G * T * vb + tile_block_lookups(p.q, vb);
+            tile_sp[sg] += tile_terms(p.q, T, vb);
             tile_cells[sg] += (double)T * vb;
         }
         for (int k = 0; k < sc.btw_cnt[sg]; ++k) {

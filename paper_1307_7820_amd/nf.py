@@ -46,7 +46,7 @@ EXPORTS = [
     "nf_fold_dev", "nf_fold_dev_noalloc", "nf_batch_create", "nf_batch_run", "nf_batch_scores", "nf_batch_table",
     "nf_batch_info", "nf_batch_structures", "nf_batch_destroy", "nf_fold_batch", "nf_serve_config", "nf_fold_bytes",
     "nf_submit", "nf_poll", "nf_wait", "nf_poll_ex", "nf_serve_stats", "nf_autotune_q",
-    "nf_autotune_target", "nf_autotune", "nf_profile_fold",
+    "nf_autotune_target", "nf_autotune", "nf_profile_fold", "nf_lds_gather_rate",
 ]
 
 
@@ -122,6 +122,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "nf_autotune_target": (c_int, [c_int, c_int]),
         "nf_autotune": (c_int, [c_int, c_int, c_int, c_int]),
         "nf_profile_fold": (c_int, [vp, c_int, c_int, c_int, vp, ctypes.POINTER(KernelProfile)]),
+        "nf_lds_gather_rate": (c_int, [c_int, c_int, ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -477,3 +478,11 @@ def nf_profile_fold(d_codes, n: int, q: int = 0, reps: int = 1, stream=None) -> 
     out = KernelProfile()
     _check(load().nf_profile_fold(p, n, q, reps, _stream_handle(stream), ctypes.byref(out)))
     return out
+
+
+def nf_lds_gather_rate(table_bytes: int = 16384, row_bytes: int = 0) -> float:
+    """LDS 1-byte gathers per second the device sustains over a table of
+    table_bytes (uniform offsets, or one row of row_bytes per wavefront load)."""
+    out = ctypes.c_double()
+    _check(load().nf_lds_gather_rate(table_bytes, row_bytes, ctypes.byref(out)))
+    return out.value
