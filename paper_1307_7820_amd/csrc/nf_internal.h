@@ -17,19 +17,22 @@
 // writes are contiguous.
 //
 // Packed state of a finished off-diagonal tile (A, B) (Lemma 1: neighbours
-// differ by 0 or 1):
-//   row state (group k of the tile's columns, row i): two words
-//       base = F(a, BT+kq)                       (Eq. 3 "D(i,l)")
-//       bits = h << (q-1), bit p-1 of h = F(a, BT+kq+p) - F(a, BT+kq+p-1)
+// differ by 0 or 1), one 32-bit word per row and group and per column and
+// group:
+//   row word (group k of the tile's columns, row i):
+//       bits 31..16 = h << (q-1), bit p-1 of h = F(a, BT+kq+p) - F(a, BT+kq+p-1)
+//       bits 15..0  = F(a, BT+kq)                (Eq. 3 "D(i,l)")
 //   column word (group k of the tile's rows, column j):
 //       bits 31..16 = F(AT+kq, b)                (Eq. 3 "D(l+1,j)")
 //       bits 15..0  = c, bit p-1 of c = F(AT+kq+p-1, b) - F(AT+kq+p, b)
-// Per tile the row block is [bases: k][64] followed by [bits: k][64] and the
-// column block is [k][64] (rows/columns >= T unused), so one group of one tile
-// is one 256-byte line.  The Four-Russians step of Eq. 3 for cell (a, b) and
-// group K is then
-//     base + (cw >> 16) + R[bits + (cw & 0xffff)]
-// and row words, read wave-uniformly, need no unpacking.
+// Scores are below 2^15 and h << (q-1) | c below 2^16 for q <= 9.  Per tile
+// the row block and the column block are each [k][64] (rows/columns >= T
+// unused), so one group of one tile is one 256-byte line.  The Four-Russians
+// step of Eq. 3 for cell (a, b) and group K is then
+//     (rw & 0xffff) + (cw >> 16) + R[(rw >> 16) + (cw & 0xffff)]
+// with the row word rw read wave-uniformly.  Every such term is one split of
+// Eq. 1, so it is at most F(a, b) < 2^15: the low half of rw + (cw >> 16) + R
+// holds it without a carry, whatever the high half of rw holds.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -51,7 +54,7 @@ constexpr int kTileCells = 64 * 64;
 __host__ __device__ constexpr int groups_per_tile(int q) { return 64 / q; }
 __host__ __device__ constexpr int tile_size(int q) { return (64 / q) * q; }
 __host__ __device__ constexpr int state_words(int q) { return (64 / q) * 64; }  // column block
-__host__ __device__ constexpr int row_words(int q) { return 2 * state_words(q); }  // row block
+__host__ __device__ constexpr int row_words(int q) { return state_words(q); }      // row block
 __host__ __device__ inline long long tile_index(int NT, int A, int d)
 {
     return (long long)d * NT - (long long)d * (d - 1) / 2 + A;

@@ -48,6 +48,27 @@ __device__ __forceinline__ const NF_CONST T* as_const(const T* p)
     return (const NF_CONST T*)p;
 }
 
+// R index of a row word held in a scalar register and a column word: bits
+// 31..16 of the row word plus bits 15..0 of the column word, one VALU
+// instruction (SDWA selects both halves; an ALU operation, not a load).
+__device__ __forceinline__ uint32_t r_index_s(uint32_t rw, uint32_t cw)
+{
+    uint32_t idx;
+    __asm__("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:WORD_0"
+            : "=v"(idx)
+            : "s"(rw), "v"(cw));
+    return idx;
+}
+
+// max of the low 16 bits of a, b and c as unsigned numbers, one VALU
+// instruction (the high halves of the operands are ignored).
+__device__ __forceinline__ uint32_t max3_u16(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t d;
+    __asm__("v_max3_u16 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 // Copy the q-dependent R table (RSZ bytes) into LDS.
 template <int RSZ>
 __device__ __forceinline__ void load_R(uint8_t* Rl, const uint8_t* __restrict__ Rg, int nthr)
@@ -67,6 +88,12 @@ __device__ __forceinline__ void load_R(uint8_t* Rl, const uint8_t* __restrict__ 
 //     F(a, Cq') + F(Cq', b) + R[h][c].
 // With NS > 1 the caller's share is every NS-th group of the flattened
 // (C, k) sequence, starting at group h.
+//
+// A lookup is three VALU instructions' worth: the R index (one SDWA add of
+// the scalar row word's high half and the column word's low half), one
+// 3-input add of the whole row word, the column base and R (its low half is
+// the split's value, see the packed words), and half of a 16-bit 3-input max
+// over two groups.  acc holds its maxima in the low 16 bits.
 template <int Q, int RPW, int NS>
 __device__ __forceinline__ void between_accumulate(int (&acc)[RPW], const uint8_t* Rl,
                                                    const uint32_t* __restrict__ RS,
@@ -76,23 +103,74 @@ __device__ __forceinline__ void between_accumulate(int (&acc)[RPW], const uint8_
     constexpr int G = groups_per_tile(Q);
     constexpr int SW = state_words(Q);
     constexpr int RW = row_words(Q);
-    for (int C = c0; C < c1; ++C) {
-        const NF_CONST uint32_t* rb = as_const(RS + tile_index(NT, A, C - A) * RW + r0);  // bases
-        const NF_CONST uint32_t* rh = rb + G * 64;                                         // bits
-        const NF_GLOBAL uint32_t* cs = as_global(CS + tile_index(NT, C, B - C) * SW + j);
-        const int k0 = (G % NS == 0) ? h : ((h - (C - c0) * G) % NS + NS) % NS;
-#pragma unroll 2
-        for (int k = k0; k < G; k += NS) {
-            const uint32_t cw = cs[k * 64];
-            const uint32_t clo = cw & 0xffffu;
-            const int chi = (int)(cw >> 16);
+    if constexpr (G % NS == 0) {
+        // every tile gives this wave the same KPT groups k = h, h+NS, ...,
+        // taken KB at a time (KB * RPW row words fit the scalar registers):
+        // all the row words (scalar loads) and column words of a batch are
+        // loaded before its first lookup, so the wait for the scalar loads,
+        // which also waits for the LDS gathers in flight, comes once per
+        // batch; the next batch's column words are loaded while this batch's
+        // lookups run
+        constexpr int KPT = G / NS;
+        constexpr int KB = KPT % 4 == 0 ? 4 : (KPT % 2 == 0 ? 2 : 1);
+        constexpr int NBT = KPT / KB;  // batches per tile
+        uint32_t cwn[KB];
+        auto load_cw = [&](int C, int u0) {
+            const NF_GLOBAL uint32_t* cs = as_global(CS + tile_index(NT, C, B - C) * SW + j);
 #pragma unroll
-            for (int r = 0; r < RPW; ++r) {
-                const int v = Rl[rh[k * 64 + r] + clo];
-                acc[r] = max(acc[r], (int)rb[k * 64 + r] + chi + v);
+            for (int v = 0; v < KB; ++v) cwn[v] = cs[(h + (u0 + v) * NS) * 64];
+        };
+        if (c0 < c1) load_cw(c0, 0);
+        for (int C = c0; C < c1; ++C) {
+            const NF_CONST uint32_t* rs = as_const(RS + tile_index(NT, A, C - A) * RW + r0);
+#pragma unroll
+            for (int bt = 0; bt < NBT; ++bt) {
+                const int u0 = bt * KB;
+                uint32_t cw[KB], rw[KB][RPW];
+#pragma unroll
+                for (int v = 0; v < KB; ++v) cw[v] = cwn[v];
+#pragma unroll
+                for (int v = 0; v < KB; ++v)
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) rw[v][r] = rs[(h + (u0 + v) * NS) * 64 + r];
+                if (bt + 1 < NBT)
+                    load_cw(C, u0 + KB);
+                else if (C + 1 < c1)
+                    load_cw(C + 1, 0);
+#pragma unroll
+                for (int v = 0; v < KB; v += 2) {
+                    const uint32_t chi0 = cw[v] >> 16;
+                    const uint32_t chi1 = v + 1 < KB ? cw[v + 1] >> 16 : 0u;
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) {
+                        const uint32_t t0 = rw[v][r] + chi0 + Rl[r_index_s(rw[v][r], cw[v])];
+                        const uint32_t t1 =
+                            v + 1 < KB ? rw[v + 1][r] + chi1 + Rl[r_index_s(rw[v + 1][r], cw[v + 1])] : 0u;
+                        acc[r] = (int)max3_u16((uint32_t)acc[r], t0, t1);
+                    }
+                }
+            }
+        }
+    } else {
+        for (int C = c0; C < c1; ++C) {
+            const NF_CONST uint32_t* rs = as_const(RS + tile_index(NT, A, C - A) * RW + r0);
+            const NF_GLOBAL uint32_t* cs = as_global(CS + tile_index(NT, C, B - C) * SW + j);
+            const int k0 = ((h - (C - c0) * G) % NS + NS) % NS;
+#pragma unroll 2
+            for (int k = k0; k < G; k += NS) {
+                const uint32_t cw = cs[k * 64];
+                const uint32_t chi = cw >> 16;
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) {
+                    const uint32_t rw = rs[k * 64 + r];
+                    const uint32_t t = rw + chi + Rl[r_index_s(rw, cw)];
+                    acc[r] = (int)max3_u16((uint32_t)acc[r], t, 0u);
+                }
             }
         }
     }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) acc[r] &= 0xffff;
 }
 
 __global__ void k_precompute_R(int q, uint8_t* __restrict__ R)
@@ -272,7 +350,7 @@ constexpr int kNeg = -(1 << 20);  // stands for minus infinity; sums stay far fr
 template <int Q>
 __device__ __forceinline__ int rlookup(const uint8_t* Rl, uint32_t rw, uint32_t cw)
 {
-    return (int)((rw >> 16) + (cw >> 16)) + (int)Rl[(rw & 0xffffu) + (cw & 0xffffu)];
+    return (int)((rw & 0xffffu) + (cw >> 16)) + (int)Rl[(rw >> 16) + (cw & 0xffffu)];
 }
 
 // max of v over the 8 lanes l ^ {8, 16, 32} (lanes 8g + c, g = 0..7)
@@ -298,7 +376,7 @@ struct TileLds {
     static constexpr int kLS = 68;
     int32_t Lp[64 * kLS];
     uint32_t LW[kBlockFR ? G * 64 : 4];  // LW[k*64 + 8g + b]: row word of row 8b+g, group k, tile (A, A)
-    uint2 EB[kStageEdges ? 2 * G * 64 : 1];      // EB[(e*G + k)*64 + row] = {base, bits}, end tile e
+    uint32_t EB[kStageEdges ? 2 * G * 64 : 1];  // EB[(e*G + k)*64 + row] = row word, end tile e
     uint32_t EC[kStageEdges ? 2 * G * 64 : 1];  // EC[(e*G + k)*64 + col] = column word, end tile e
     int32_t Qs[2][64];    // Q of the row being closed (double-buffered)
     int32_t hrow[64];
@@ -331,7 +409,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     int32_t* Xs = s.Xs;
     int32_t* Lp = s.Lp;
     uint32_t* LW = s.LW;
-    uint2* EB = s.EB;
+    uint32_t* EB = s.EB;
     uint32_t* EC = s.EC;
     int32_t (*Qs)[64] = s.Qs;
     int32_t* hrow = s.hrow;
@@ -424,7 +502,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     // accumulator is below, so every lookup can run unguarded.  (The loads
     // stay inside the fold's tile arrays either way.)
     constexpr int kIter = kStageEdges ? (2 * G * 64 + kTileThreads - 1) / kTileThreads : 1;
-    uint32_t rb[kIter], rh[kIter], cw[kIter];
+    uint32_t rb[kIter], cw[kIter];
     if constexpr (kStageEdges) {
 #pragma unroll
         for (int u = 0; u < kIter; ++u) {
@@ -432,11 +510,9 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             const int eg = x >> 6, r = x & 63;
             const int e = eg / G, k = eg - e * G;
             const int C = e == 0 ? A + 1 : B - 1;
-            rb[u] = rh[u] = cw[u] = 0;
+            rb[u] = cw[u] = 0;
             if (x < 2 * G * 64) {
-                const NF_GLOBAL uint32_t* rs = RSr + tile_index(f.NT, A, C - A) * RW + k * 64 + r;
-                rb[u] = rs[0];
-                rh[u] = rs[G * 64];
+                rb[u] = RSr[tile_index(f.NT, A, C - A) * RW + k * 64 + r];
                 cw[u] = CSr[tile_index(f.NT, C, B - C) * SW + k * 64 + r];
             }
         }
@@ -466,7 +542,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             const int x = tid + u * kTileThreads;
             if (x < 2 * G * 64) {
                 const bool live = (x >> 6) < nedge * G;
-                EB[x] = live ? make_uint2(rb[u], rh[u]) : make_uint2(0u, 0u);
+                EB[x] = live ? rb[u] : 0u;
                 EC[x] = live ? cw[u] : 0u;
             }
         }
@@ -497,7 +573,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                 for (int p = 1; p <= M; ++p)
                     h |= (uint32_t)(Lp[(top + p) * LS + pos] > Lp[(top + p - 1) * LS + pos]) << (p - 1);
             }
-            LW[x] = ((uint32_t)base << 16) | (h << M);
+            LW[x] = ((h << M) << 16) | (uint32_t)base;
         }
     }
 
@@ -508,10 +584,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
         for (int x = 0; x < NE; ++x) ecw[x] = EC[x * 64 + j];
     }
     // one end-tile lookup (edge e, group k) for row 8b + g
-    auto edge = [&](int x, int b) {
-        const uint2 rw = EB[x * 64 + 8 * b + g];
-        return (int)rw.x + (int)(ecw[x] >> 16) + (int)Rl[rw.y + (ecw[x] & 0xffffu)];
-    };
+    auto edge = [&](int x, int b) { return rlookup<Q>(Rl, EB[x * 64 + 8 * b + g], ecw[x]); };
 
     if constexpr (kStageEdges) {
         // rows of block 7 take their end-tile groups here, the other blocks
@@ -522,17 +595,12 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
         // q < 4: the end tiles' words are read straight from memory
         for (int e = 0; e < nedge; ++e) {
             const int C = e == 0 ? A + 1 : B - 1;
-            const NF_GLOBAL uint32_t* rb = RSr + tile_index(f.NT, A, C - A) * RW;
+            const NF_GLOBAL uint32_t* rs = RSr + tile_index(f.NT, A, C - A) * RW;
             const NF_GLOBAL uint32_t* cs = CSr + tile_index(f.NT, C, B - C) * SW;
             for (int k = 0; k < G; ++k) {
                 const uint32_t cw = cs[k * 64 + j];
-                const uint32_t clo = cw & 0xffffu;
-                const int chi = (int)(cw >> 16);
 #pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    const int r = 8 * b + g;
-                    acc[b] = max(acc[b], (int)rb[k * 64 + r] + chi + (int)Rl[rb[G * 64 + k * 64 + r] + clo]);
-                }
+                for (int b = 0; b < 8; ++b) acc[b] = max(acc[b], rlookup<Q>(Rl, rs[k * 64 + 8 * b + g], cw));
             }
         }
     }
@@ -565,8 +633,8 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
         if (i < T && j < T && (i == T - 1 || j == 0)) acc[b] = max(acc[b], bp + halo);
     }
 
-    // outputs: dense cells, row words (bases, then bits at + G*64), column
-    // words, written after the row loop (global address space: generic
+    // outputs: dense cells, row words, column words, written after the row
+    // loop (global address space: generic
     // accesses also count against the LDS counter that barriers wait on)
     const long long t_idx = tile_index(f.NT, A, d);
     NF_GLOBAL int16_t* Fw = (NF_GLOBAL int16_t*)f.F;
@@ -579,12 +647,12 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     // end-tile row words of the share of row (bb, r): groups x = r + 8m of
     // block bb-1, loaded one row step ahead of their use
     constexpr int kEPer = (NE + 7) / 8;
-    uint2 erw[kEPer];
+    uint32_t erw[kEPer];
     auto fetch_edges = [&](int bb, int r) {
 #pragma unroll
         for (int m = 0; m < kEPer; ++m) {
             const int x = r + 8 * m;
-            erw[m] = (bb >= 1 && x < NE) ? EB[x * 64 + 8 * (bb - 1) + g] : make_uint2(0u, 0u);
+            erw[m] = (bb >= 1 && x < NE) ? EB[x * 64 + 8 * (bb - 1) + g] : 0u;
         }
     };
     if constexpr (kStageEdges) fetch_edges(7, 7);
@@ -619,8 +687,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
 #pragma unroll
                     for (int m = 0; m < kEPer; ++m) {
                         const int x = rr + 8 * m;
-                        if (x < NE)
-                            ev = max(ev, (int)erw[m].x + (int)(ecw[x] >> 16) + (int)Rl[erw[m].y + (ecw[x] & 0xffffu)]);
+                        if (x < NE) ev = max(ev, rlookup<Q>(Rl, erw[m], ecw[x]));
                     }
                 }
                 fetch_edges(rr > 0 ? blk : blk - 1, rr > 0 ? rr - 1 : 7);
@@ -699,14 +766,12 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                 if (ln < T && (ln % Q) == 0) {
                     uint32_t h = 0;
                     if constexpr (M > 0) h = (uint32_t)(diff >> (ln + 1)) & ((1u << M) - 1u);
-                    RSw[(ln / Q) * 64 + i] = (uint32_t)v;
-                    RSw[G * 64 + (ln / Q) * 64 + i] = h << M;
+                    RSw[(ln / Q) * 64 + i] = ((h << M) << 16) | (uint32_t)v;
                 }
             } else if (ln < G) {
                 // padding row (T < 64): readers load whole 64-row lines, so
                 // give it words that keep their sums bounded and R in range
                 RSw[ln * 64 + i] = 0;
-                RSw[G * 64 + ln * 64 + i] = 0;
             }
         }
     }

@@ -307,8 +307,8 @@ def nf_fold_dev(d_codes, n: int, q: int = 0, d_score=None, d_S=None, stream=None
 
 def nf_fold_dev_noalloc(d_codes, n: int, q: int = 0, d_score=None, d_S=None, stream=None) -> None:
     """nf_fold_dev that allocates nothing: every buffer beyond the arguments
-    lives in the library's static device scratch (n up to about 3200 at
-    q = 8).  Same argument checks as nf_fold_dev."""
+    lives in the library's static device scratch (n up to 3455 at q = 8).
+    Same argument checks as nf_fold_dev."""
     if n < 0:
         raise ValueError("n must be >= 0")
     pc = _dev_ptr(d_codes, "uint8", n, "d_codes")
