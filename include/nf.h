@@ -285,10 +285,20 @@ int nf_autotune_q(int n);
  * NF_BETWEEN_TARGET, if set, overrides every value.  NF_E_INVAL for n or q
  * out of range. */
 int nf_autotune_target(int n, int q);
+/* Whether a single fold of length n at group width q (0 = what q = 0
+ * resolves to) runs its fused wavefront steps in the wide shape: the same
+ * kernel code held to fewer registers so that a CU takes three workgroups
+ * instead of two, which speeds the between-group lookups of long folds and
+ * slows each tile finish.  Only at q = 8.  The tuned choice of n's bucket
+ * (fourth column of the cache file: 1 wide, 0 not) if it was tuned at this q,
+ * else wide for n >= 8192; NF_STAGE_WIDE=0|1 overrides.  Returns 1 or 0, or
+ * NF_E_INVAL for n or q out of range. */
+int nf_autotune_wide(int n, int q);
 /* Time the fill at length n (reps folds each, after one warm-up fold): first
  * q in qmin..qmax at the default target, then the targets 1024, 256, 512 and
- * 2048 at the fastest q.  Records both in the in-memory cache (and in the
- * cache file if set).  Returns the chosen q. */
+ * 2048 at the fastest q, then (q = 8) the other fused-step shape.  Records
+ * all three in the in-memory cache (and in the cache file if set).  Returns
+ * the chosen q. */
 int nf_autotune(int n, int qmin, int qmax, int reps);
 
 /* ---- Diagnostics ----
@@ -315,6 +325,7 @@ typedef struct {
     double splits[4];
     double cells[4];
     int q, tile, tiles_per_side, stages;
+    int wide; /* 1 when the fused steps ran in the wide shape (nf_autotune_wide) */
 } nf_kernel_profile_t;
 int nf_profile_fold(const uint8_t* d_codes, int n, int q, int reps, void* stream, nf_kernel_profile_t* out);
 

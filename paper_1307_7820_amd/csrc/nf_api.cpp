@@ -470,6 +470,16 @@ int nf_autotune_target(int n, int q)
     return between_target(n, q);
 }
 
+int nf_autotune_wide(int n, int q)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (n < 0 || n > NF_MAX_N) return fail(NF_E_INVAL, "length %d out of range", n);
+    int rc = check_q(q);
+    if (rc) return rc;
+    return stage_wide(n, resolve_q(q, n)) ? 1 : 0;
+}
+
 int nf_autotune(int n, int qmin, int qmax, int reps)
 {
     std::lock_guard<std::recursive_mutex> lk(g_api);
@@ -498,6 +508,7 @@ int nf_profile_fold(const uint8_t* d_codes, int n, int q, int reps, void* stream
     out->tile = tile_size(q);
     out->tiles_per_side = g.NT;
     out->stages = p->sc.stages;
+    out->wide = p->wide ? 1 : 0;
     return plan_profile(*p, s, reps, out);
 }
 

@@ -161,9 +161,15 @@ static_assert(sizeof(TileWork) == 80, "TileWork layout");
 static_assert(sizeof(BetweenWork) == 80, "BetweenWork layout");
 
 // One fused wavefront step: ntile tile finishes and nbtw between chunks of
-// the next diagonal in one launch of kTileThreads-thread workgroups.
-hipError_t launch_stage(int q, const TileWork* titems, int ntile, const BetweenWork* bitems, int nbtw,
+// the next diagonal in one launch of kTileThreads-thread workgroups.  wide
+// (q = 8 only; ignored otherwise) selects the shape that fits three
+// workgroups per CU instead of two.
+hipError_t launch_stage(int q, bool wide, const TileWork* titems, int ntile, const BetweenWork* bitems, int nbtw,
                         const uint8_t* R, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Whether a single fold of length n at q runs the wide fused step: the tuned
+// choice of n's length bucket if one was tuned at this q, else n >= 8192 at
+// q = 8 (NF_STAGE_WIDE=0|1 overrides).
+bool stage_wide(int n_single, int q);
 
 // Plain between-group maxima from the dense table (no R): the ablation of the
 // lookup.  q must give 64-post tiles (1, 2, 4, 8).

@@ -19,6 +19,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 namespace nf {
 
 namespace {
@@ -264,7 +266,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(const TileWork* __restrict__ 
 template <int Q, int RPW, int NS>
 __device__ __forceinline__ void between_body(const BetweenWork& it, const uint8_t* Rl,
                                              const uint32_t* RS, const uint32_t* CS, int wave, int j,
-                                             int32_t* red)
+                                             uint16_t* red)
 {
     constexpr int NB = 64 / RPW;
     static_assert(NS == 1 || NS == 2, "one or two wavefronts per row block");
@@ -277,12 +279,12 @@ __device__ __forceinline__ void between_body(const BetweenWork& it, const uint8_
     if constexpr (NS == 2) {
         if (h == 1) {
 #pragma unroll
-            for (int r = 0; r < RPW; ++r) red[(r0 + r) * 64 + j] = acc[r];
+            for (int r = 0; r < RPW; ++r) red[(r0 + r) * 64 + j] = (uint16_t)acc[r];  // maxima < 2^15
         }
         __syncthreads();
         if (h == 1) return;
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) acc[r] = max(acc[r], red[(r0 + r) * 64 + j]);
+        for (int r = 0; r < RPW; ++r) acc[r] = max(acc[r], (int)red[(r0 + r) * 64 + j]);
     }
 
     int32_t* out = it.acc + r0 * 64 + j;
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(kBetweenThreads) void k_between(const BetweenWork* 
 {
     constexpr int RSZ = 1 << (2 * (Q - 1));
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
-    __shared__ int32_t red[kBetweenSplit == 2 ? 64 * 64 : 1];
+    __shared__ uint16_t red[kBetweenSplit == 2 ? 64 * 64 : 1];
 
     const BetweenWork& it = items[blockIdx.x];
     load_R<RSZ>(Rl, Rg, kBetweenThreads);
@@ -364,12 +366,16 @@ __device__ __forceinline__ int max_over_groups(int v)
     return max((int)p32[0], (int)p32[1]);
 }
 
-template <int Q>
+// kLean: the finish's lean form for the wide fused step (fewer registers and
+// less LDS): finished cells kept as 16-bit values and the end tiles' column
+// words read from LDS a row step ahead instead of held in registers.
+template <int Q, bool kLean>
 struct TileLds {
     static constexpr int G = groups_per_tile(Q);
     static constexpr bool kBlockFR = (8 % Q) == 0;  // q-groups tile the 8-row blocks
     static constexpr bool kStageEdges = G <= 16;    // end-tile words fit in LDS
-    int32_t Xs[64 * 64];  // finished cells, row-major
+    using Cell = typename std::conditional<kLean, int16_t, int32_t>::type;
+    Cell Xs[64 * 64];  // finished cells, row-major (values < 2^15)
     // Lp[i*kLS + 8g + b] = L(8b+g, i) for 8b+g < i < T, else -inf; the row
     // stride kLS = 68 keeps 16-byte rows and spreads the transposed writes
     // over the banks
@@ -392,8 +398,8 @@ struct TileLds {
 // the loads that need the main-diagonal tiles (A, A) and (B, B); wait_main()
 // before the loads that need the tiles of diagonal d-1 and the between-group
 // maxima.  Both are collective (every thread calls them).
-template <int Q, bool kLoadR, class Pre, class Main>
-__device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const uint8_t* Rg, TileLds<Q>& s,
+template <int Q, bool kLoadR, bool kLean, class Pre, class Main>
+__device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const uint8_t* Rg, TileLds<Q, kLean>& s,
                                           Pre&& wait_pre, Main&& wait_main)
 {
     constexpr int M = Q - 1;
@@ -401,12 +407,14 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     constexpr int T = tile_size(Q);
     constexpr int SW = state_words(Q);
     constexpr int RW = row_words(Q);
-    constexpr bool kBlockFR = TileLds<Q>::kBlockFR;
+    using Lds = TileLds<Q, kLean>;
+    using Cell = typename Lds::Cell;
+    constexpr bool kBlockFR = Lds::kBlockFR;
     constexpr int GPB = kBlockFR ? 8 / Q : 1;  // groups per block
-    constexpr bool kStageEdges = TileLds<Q>::kStageEdges;
+    constexpr bool kStageEdges = Lds::kStageEdges;
     constexpr int NE = kStageEdges ? 2 * G : 1;  // end-tile lookups per row (both edges)
-    constexpr int LS = TileLds<Q>::kLS;
-    int32_t* Xs = s.Xs;
+    constexpr int LS = Lds::kLS;
+    Cell* Xs = s.Xs;
     int32_t* Lp = s.Lp;
     uint32_t* LW = s.LW;
     uint32_t* EB = s.EB;
@@ -577,14 +585,21 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
         }
     }
 
-    // column words of the end tiles at this lane's column (fixed for the tile)
-    uint32_t ecw[NE];
-    if constexpr (kStageEdges) {
+    // column words of the end tiles at this lane's column (fixed for the
+    // tile): in registers, or in the lean form read from LDS where used
+    constexpr int NEC = (kStageEdges && !kLean) ? NE : 1;
+    uint32_t ecw[NEC];
+    if constexpr (kStageEdges && !kLean) {
 #pragma unroll
         for (int x = 0; x < NE; ++x) ecw[x] = EC[x * 64 + j];
     }
-    // one end-tile lookup (edge e, group k) for row 8b + g
-    auto edge = [&](int x, int b) { return rlookup<Q>(Rl, EB[x * 64 + 8 * b + g], ecw[x]); };
+    auto col_word = [&](int x) -> uint32_t {
+        if constexpr (kStageEdges && !kLean) return ecw[x];
+        else return EC[x * 64 + j];
+    };
+    // one end-tile lookup (edge e, group k: x = e*G + k) for row 8b + g and
+    // this lane's column
+    auto edge = [&](int x, int b) { return rlookup<Q>(Rl, EB[x * 64 + 8 * b + g], col_word(x)); };
 
     if constexpr (kStageEdges) {
         // rows of block 7 take their end-tile groups here, the other blocks
@@ -644,15 +659,17 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     // ---- rows bottom-up.  Rows >= T (only when T < 64) are inert: their
     // pushes are -inf in Lp and their pairing into row T-1 is skipped.
     if (g == 7) Qs[1][j] = acc[7];  // row 63: Q complete (no row below)
-    // end-tile row words of the share of row (bb, r): groups x = r + 8m of
-    // block bb-1, loaded one row step ahead of their use
+    // end-tile row and column words of the share of row (bb, r): groups
+    // x = r + 8m of block bb-1, loaded one row step ahead of their use
     constexpr int kEPer = (NE + 7) / 8;
-    uint32_t erw[kEPer];
+    uint32_t erw[kEPer], erc[kEPer];
     auto fetch_edges = [&](int bb, int r) {
 #pragma unroll
         for (int m = 0; m < kEPer; ++m) {
             const int x = r + 8 * m;
-            erw[m] = (bb >= 1 && x < NE) ? EB[x * 64 + 8 * (bb - 1) + g] : 0u;
+            const bool live = bb >= 1 && x < NE;
+            erw[m] = live ? EB[x * 64 + 8 * (bb - 1) + g] : 0u;
+            if constexpr (kLean) erc[m] = live ? EC[x * 64 + j] : 0u;
         }
     };
     if constexpr (kStageEdges) fetch_edges(7, 7);
@@ -687,7 +704,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
 #pragma unroll
                     for (int m = 0; m < kEPer; ++m) {
                         const int x = rr + 8 * m;
-                        if (x < NE) ev = max(ev, rlookup<Q>(Rl, erw[m], ecw[x]));
+                        if (x < NE) ev = max(ev, rlookup<Q>(Rl, erw[m], kLean ? erc[m] : col_word(x)));
                     }
                 }
                 fetch_edges(rr > 0 ? blk : blk - 1, rr > 0 ? rr - 1 : 7);
@@ -741,7 +758,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                     Qs[(i - 1) & 1][j] = qv;
                 }
             }
-            if (g == 0) Xs[i * 64 + j] = xi;
+            if (g == 0) Xs[i * 64 + j] = (Cell)xi;
             __syncthreads();
         }
     }
@@ -783,7 +800,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
 #pragma unroll
             for (int p = 1; p <= M; ++p)
                 cbits |= (uint32_t)(Xs[(top + p - 1) * 64 + jj] > Xs[(top + p) * 64 + jj]) << (p - 1);
-            CSw[k * 64 + jj] = ((uint32_t)Xs[top * 64 + jj] << 16) | cbits;
+            CSw[k * 64 + jj] = ((uint32_t)(uint16_t)Xs[top * 64 + jj] << 16) | cbits;
         } else {
             CSw[k * 64 + jj] = 0;  // padding column, as for padding rows
         }
@@ -796,30 +813,44 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
 {
     constexpr int RSZ = 1 << (2 * (Q - 1));
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
-    __shared__ __align__(16) TileLds<Q> s;
-    tile_body<Q, true>(items[blockIdx.x], Rl, Rg, s, [] {}, [] {});
+    __shared__ __align__(16) TileLds<Q, false> s;
+    tile_body<Q, true, false>(items[blockIdx.x], Rl, Rg, s, [] {}, [] {});
 }
 
 // One wavefront step in one launch: workgroups [0, ntile) finish the tiles
 // of diagonal s, the rest run the between chunks of diagonal s+1 (which only
 // read diagonals <= s-1 and write the other half of the accumulators).
-template <int Q>
-__global__ __launch_bounds__(kTileThreads) void k_stage(const TileWork* __restrict__ titems, int ntile,
+//
+// Two shapes of the same code.  The default leaves the register count to the
+// compiler (two workgroups per CU at q = 8: the finish's registers and LDS
+// bound it), which keeps the finish, the fold's critical path, fastest.  The
+// wide shape (q = 8 only) holds each workgroup to 80 VGPRs (the compiler
+// spills a few registers to scratch) so that a CU takes three, six
+// wavefronts per SIMD: the between chunks, which bound long folds, then run
+// faster while each finish runs slower.  (Measured on MI355X: n = 16000
+// 13.2 -> 12.2 ms, n = 6000 2.21 -> 2.34 ms.)
+template <int Q, bool kWide>
+constexpr int kStageWavesPerSimd = (Q == 8 && kWide) ? 6 : 1;
+
+template <int Q, bool kWide>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(kStageWavesPerSimd<Q, kWide>)))
+void k_stage(const TileWork* __restrict__ titems, int ntile,
                                                         const BetweenWork* __restrict__ bitems,
                                                         const uint8_t* __restrict__ Rg)
 {
     constexpr int RSZ = 1 << (2 * (Q - 1));
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
-    __shared__ __align__(16) TileLds<Q> s;
+    __shared__ __align__(16) TileLds<Q, kWide> s;
     const int b = blockIdx.x;
     if (b < ntile) {
-        tile_body<Q, true>(titems[b], Rl, Rg, s, [] {}, [] {});
+        tile_body<Q, true, kWide>(titems[b], Rl, Rg, s, [] {}, [] {});
     } else {
         load_R<RSZ>(Rl, Rg, kTileThreads);
         __syncthreads();
         const BetweenWork& it = bitems[b - ntile];
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        between_body<Q, 16, kTileThreads / 64 / 4>(it, Rl, it.f.RS, it.f.CS, wave, threadIdx.x & 63, s.Xs);
+        between_body<Q, 16, kTileThreads / 64 / 4>(it, Rl, it.f.RS, it.f.CS, wave, threadIdx.x & 63,
+                                                   reinterpret_cast<uint16_t*>(s.Xs));
     }
 }
 
@@ -929,14 +960,16 @@ template <int Q>
 hipError_t stage_q(const TileWork* t, int nt, const BetweenWork* b, int nb, const uint8_t* R, hipStream_t s,
                    hipEvent_t e0, hipEvent_t e1)
 {
-    return launch_k(k_stage<Q>, dim3(nt + nb), dim3(kTileThreads), s, e0, e1, t, nt, b, R);
+    return launch_k(k_stage<Q, false>, dim3(nt + nb), dim3(kTileThreads), s, e0, e1, t, nt, b, R);
 }
 }  // namespace
 
-hipError_t launch_stage(int q, const TileWork* titems, int ntile, const BetweenWork* bitems, int nbtw,
+hipError_t launch_stage(int q, bool wide, const TileWork* titems, int ntile, const BetweenWork* bitems, int nbtw,
                         const uint8_t* R, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (ntile + nbtw <= 0) return hipSuccess;
+    if (wide && q == 8)
+        return launch_k(k_stage<8, true>, dim3(ntile + nbtw), dim3(kTileThreads), s, e0, e1, titems, ntile, bitems, R);
     switch (q) {
     case 1: return stage_q<1>(titems, ntile, bitems, nbtw, R, s, e0, e1);
     case 2: return stage_q<2>(titems, ntile, bitems, nbtw, R, s, e0, e1);

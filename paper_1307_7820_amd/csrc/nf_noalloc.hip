@@ -186,8 +186,9 @@ extern "C" int nf_fold_dev_noalloc(const uint8_t* d_codes, int n, int q, int32_t
     hipLaunchKernelGGL(k_single_items, dim3(S.NT), dim3(256), 0, s, S, fd, acc, diag, tiles, btw, fdp);
     HIPCHK(hipGetLastError());
     HIPCHK(launch_diag(q, diag, S.NT, s));
+    const bool wide = stage_wide(n, q);
     for (int sg = 1; sg < S.NT; ++sg)
-        HIPCHK(launch_stage(q, tiles + S.finish_offset(sg), S.finishes(sg), btw + S.between_offset(sg),
+        HIPCHK(launch_stage(q, wide, tiles + S.finish_offset(sg), S.finishes(sg), btw + S.between_offset(sg),
                             S.between_count(sg), R, s));
     if (d_score) HIPCHK(launch_scores(fdp, 1, d_score, s));
     if (d_S && n > 0) HIPCHK(launch_expand(fd.F, g.ld, n, d_S, s));

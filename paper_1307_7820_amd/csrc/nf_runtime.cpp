@@ -228,6 +228,16 @@ int between_target(int n_single, int q)
     return kDefaultTarget;
 }
 
+bool stage_wide(int n_single, int q)
+{
+    if (q != 8 || n_single < 0) return false;
+    if (const char* e = getenv("NF_STAGE_WIDE")) return atoi(e) != 0;
+    load_tune_file();
+    const int b = bucket_of(n_single);
+    if (ctx().tuned_wide[b] && ctx().tuned_q[b] == q) return ctx().tuned_wide[b] == 2;
+    return n_single >= 8192;
+}
+
 // Append the between-group items of diagonal dd for the listed folds.  The
 // intermediate tiles C in [A+2, A+dd-2] of every tile are cut into chunks of
 // about equal work so that the step has roughly `target` workgroups.  Every
@@ -469,7 +479,7 @@ static int plan_enqueue_fused(Plan& p, hipStream_t s)
             if (sc.btw_cnt[0] > 0)
                 HIPCHK(launch_between(p.q, (const BetweenWork*)p.d_btw.p + sc.btw_off[0], sc.btw_cnt[0], R, s));
         } else {
-            HIPCHK(launch_stage(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg],
+            HIPCHK(launch_stage(p.q, p.wide, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg],
                                 (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R, s));
         }
     }
@@ -600,7 +610,7 @@ int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out)
                 if (fused && sg >= 1) {
                     if (sc.tile_cnt[sg] + sc.btw_cnt[sg] == 0) continue;
                     if (!pair(a, b)) return fail(NF_E_DEVICE, "event creation failed");
-                    HIPCHK(launch_stage(p.q, tw, sc.tile_cnt[sg], bw, sc.btw_cnt[sg], R, s, a, b));
+                    HIPCHK(launch_stage(p.q, p.wide, tw, sc.tile_cnt[sg], bw, sc.btw_cnt[sg], R, s, a, b));
                     recs.push_back({3, a, b, tile_lk[sg] + btw_lk[sg], tile_sp[sg], tile_cells[sg]});
                     continue;
                 }
@@ -660,8 +670,7 @@ int plan_enqueue(Plan& p, hipStream_t s)
     return NF_OK;
 }
 
-// target > 0 fixes the between chunks per step; 0 takes between_target's.
-int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out, int target)
+int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out, int target, int wide)
 {
     auto p = std::make_unique<Plan>();
     p->q = q;
@@ -674,6 +683,7 @@ int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out, int
     p->plain = plain_between_for(q);
     if (p->plain) p->mode = kModeStaged;  // the fused step has the lookup built in
     p->target = target > 0 ? target : between_target(ns.size() == 1 ? ns[0] : -1, q);
+    p->wide = ns.size() == 1 && q == 8 && (wide >= 0 ? wide > 0 : stage_wide(ns[0], q));
     build_schedule(NTs, p->target, p->sc);
     int rc = plan_allocate(*p);
     if (rc) return rc;
@@ -683,16 +693,17 @@ int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out, int
 
 // Single-fold plans are cached by (n, q) and the chunk target, least recently
 // used first out.
-int single_plan(int n, int q, Plan** out, int target)
+int single_plan(int n, int q, Plan** out, int target, int wide)
 {
     Context& c = ctx();
     if (target <= 0) target = between_target(n, q);
+    if (wide < 0) wide = (q == 8 && stage_wide(n, q)) ? 1 : 0;
     // NF_MODE and NF_BETWEEN are read when a plan is made, so they are part of the key
     const char* me = getenv("NF_MODE");
     const int mode_env = !me ? 0 : strcmp(me, "fused") == 0 ? 1 : strcmp(me, "staged") == 0 ? 2 : 0;
     const long long key = (((long long)n * 16 + q) * 2 + (plain_between_for(q) ? 1 : 0)) * 3 + mode_env;
     for (auto it = c.plans.begin(); it != c.plans.end(); ++it) {
-        if (it->first == key && it->second->target == target) {
+        if (it->first == key && it->second->target == target && it->second->wide == (wide > 0)) {
             auto ent = std::move(*it);
             c.plans.erase(it);
             c.plans.push_back(std::move(ent));
@@ -710,10 +721,10 @@ int single_plan(int n, int q, Plan** out, int target)
         c.plans.erase(c.plans.begin());
     }
     std::unique_ptr<Plan> p;
-    int rc = make_plan({n}, q, p, target);
+    int rc = make_plan({n}, q, p, target, wide);
     if (rc == NF_E_NOMEM && !c.plans.empty()) {  // drop every cached plan and retry once
         c.plans.clear();
-        rc = make_plan({n}, q, p, target);
+        rc = make_plan({n}, q, p, target, wide);
     }
     if (rc) return rc;
     c.plans.push_back({key, std::move(p)});
@@ -749,15 +760,16 @@ static void load_tune_file()
     c.tune_loaded = true;
     const char* path = getenv("NF_AUTOTUNE_CACHE");
     if (!path) return;
-    // one line per length bucket: "bucket q [target]"
+    // one line per length bucket: "bucket q [target [wide]]"
     std::ifstream in(path);
     std::string line;
     while (std::getline(in, line)) {
-        int b = -1, q = 0, t = 0;
-        const int got = sscanf(line.c_str(), "%d %d %d", &b, &q, &t);
+        int b = -1, q = 0, t = 0, w = -1;
+        const int got = sscanf(line.c_str(), "%d %d %d %d", &b, &q, &t, &w);
         if (got < 2 || b < 0 || b >= kTuneBuckets || q < NF_Q_MIN || q > NF_Q_MAX) continue;
         c.tuned_q[b] = q;
-        if (got == 3 && t > 0 && t <= (1 << 20)) c.tuned_target[b] = t;
+        if (got >= 3 && t > 0 && t <= (1 << 20)) c.tuned_target[b] = t;
+        if (got == 4 && (w == 0 || w == 1)) c.tuned_wide[b] = 1 + w;
     }
 }
 
@@ -767,7 +779,11 @@ static void save_tune_file()
     if (!path) return;
     std::ofstream out(path);
     for (int b = 0; b < kTuneBuckets; ++b)
-        if (ctx().tuned_q[b]) out << b << " " << ctx().tuned_q[b] << " " << ctx().tuned_target[b] << "\n";
+        if (ctx().tuned_q[b]) {
+            out << b << " " << ctx().tuned_q[b] << " " << ctx().tuned_target[b];
+            if (ctx().tuned_wide[b]) out << " " << ctx().tuned_wide[b] - 1;
+            out << "\n";
+        }
 }
 
 int autotune_lookup(int n)
@@ -797,10 +813,11 @@ int autotune_run(int n, int qmin, int qmax, int reps)
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     StreamFence fence{c.stream};  // the uploads read `codes`
-    // time `reps` fills of the plan for (q, target) after one warm-up fill
-    auto time_plan = [&](int q, int target, float* ms) -> int {
+    // time `reps` fills of the plan for (q, target, fused-step shape) after
+    // one warm-up fill
+    auto time_plan = [&](int q, int target, int wide, float* ms) -> int {
         Plan* p = nullptr;
-        int r = single_plan(n, q, &p, target);
+        int r = single_plan(n, q, &p, target, wide);
         if (r) return r;
         const Geom& g = p->geom[0];
         if (hipMemcpyAsync((char*)p->arena.p + g.codes_off, codes.data(), n, hipMemcpyHostToDevice, c.stream) !=
@@ -815,25 +832,31 @@ int autotune_run(int n, int qmin, int qmax, int reps)
         (void)hipEventElapsedTime(ms, e0, e1);
         return r;
     };
-    // q at the default chunk target, then the chunk target at that q; the
-    // default comes first, so a tie keeps it
+    // q at the default chunk target and step shape, then the chunk target at
+    // that q, then (q = 8) the other fused-step shape; the default comes
+    // first, so a tie keeps it
+    auto default_wide = [&](int q) { return (q == 8 && n >= 8192) ? 1 : 0; };
     int best_q = kDefaultQ, best_t = kDefaultTarget;
     float best_ms = 1e30f, ms = 0;
     for (int q = qmin; q <= qmax && !rc; ++q) {
-        if ((rc = time_plan(q, kDefaultTarget, &ms))) break;
+        if ((rc = time_plan(q, kDefaultTarget, default_wide(q), &ms))) break;
         if (ms < best_ms) {
             best_ms = ms;
             best_q = q;
         }
     }
     best_ms = 1e30f;
+    int best_w = default_wide(best_q);
     for (int t : {kDefaultTarget, 256, 512, 2048}) {
         if (rc) break;
-        if ((rc = time_plan(best_q, t, &ms))) break;
+        if ((rc = time_plan(best_q, t, best_w, &ms))) break;
         if (ms < best_ms) {
             best_ms = ms;
             best_t = t;
         }
+    }
+    if (!rc && best_q == 8) {
+        if (!(rc = time_plan(best_q, best_t, 1 - best_w, &ms)) && ms < best_ms) best_w = 1 - best_w;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -841,6 +864,7 @@ int autotune_run(int n, int qmin, int qmax, int reps)
     load_tune_file();
     c.tuned_q[bucket_of(n)] = best_q;
     c.tuned_target[bucket_of(n)] = best_t;
+    c.tuned_wide[bucket_of(n)] = best_q == 8 ? 1 + best_w : 0;
     save_tune_file();
     return best_q;
 }

@@ -101,6 +101,7 @@ struct Plan {
     int mode = kModeStaged;
     bool plain = false;  // between-group work by the plain recurrence (NF_BETWEEN=plain)
     int target = 0;      // between chunks per wavefront step the schedule was built for
+    bool wide = false;   // fused steps in the wide shape (three workgroups per CU at q = 8)
     std::vector<Geom> geom;
     std::vector<FoldDesc> h_folds;
     Schedule sc;
@@ -131,6 +132,7 @@ struct Context {
     std::vector<std::pair<long long, std::unique_ptr<Plan>>> plans;  // LRU, most recent last
     int tuned_q[kTuneBuckets] = {0};
     int tuned_target[kTuneBuckets] = {0};
+    int tuned_wide[kTuneBuckets] = {0};  // 0: not tuned, 1: default fused step, 2: wide fused step
     bool tune_loaded = false;
 };
 
@@ -162,8 +164,10 @@ int plan_mode_for(const std::vector<int>& NTs);
 // only for 64-post tiles (q = 1, 2, 4, 8), ignored otherwise.
 bool plain_between_for(int q);
 int plan_profile(Plan& p, hipStream_t s, int reps, nf_kernel_profile_t* out);
-int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out, int target = 0);
-int single_plan(int n, int q, Plan** out, int target = 0);
+// target > 0 fixes the between chunks per step; wide < 0 takes stage_wide's
+// choice for a single fold (batches always run the default fused step).
+int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out, int target = 0, int wide = -1);
+int single_plan(int n, int q, Plan** out, int target = 0, int wide = -1);
 int autotune_lookup(int n);
 int autotune_run(int n, int qmin, int qmax, int reps);
 

@@ -565,8 +565,8 @@ void engine_main()
                 size_t et = bt, eb = bb;
                 while (et < wtile.size() && wtile[et].pad0 == q) ++et;
                 while (eb < wbtw.size() && wbtw[eb].pad0 == q) ++eb;
-                ok = launch_stage(q, d_tile + bt, (int)(et - bt), d_btw + bb, (int)(eb - bb), D.R[q], D.s1) ==
-                     hipSuccess;
+                ok = launch_stage(q, false, d_tile + bt, (int)(et - bt), d_btw + bb, (int)(eb - bb), D.R[q],
+                                  D.s1) == hipSuccess;
                 bt = et;
                 bb = eb;
             }

@@ -46,7 +46,7 @@ EXPORTS = [
     "nf_fold_dev", "nf_fold_dev_noalloc", "nf_batch_create", "nf_batch_run", "nf_batch_scores", "nf_batch_table",
     "nf_batch_info", "nf_batch_structures", "nf_batch_destroy", "nf_fold_batch", "nf_serve_config", "nf_fold_bytes",
     "nf_submit", "nf_poll", "nf_wait", "nf_poll_ex", "nf_serve_stats", "nf_autotune_q",
-    "nf_autotune_target", "nf_autotune", "nf_profile_fold", "nf_lds_gather_rate",
+    "nf_autotune_target", "nf_autotune_wide", "nf_autotune", "nf_profile_fold", "nf_lds_gather_rate",
 ]
 
 
@@ -68,7 +68,7 @@ class KernelProfile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 4), ("ms", ctypes.c_double * 4),
                 ("lookups", ctypes.c_double * 4), ("splits", ctypes.c_double * 4), ("cells", ctypes.c_double * 4),
                 ("q", ctypes.c_int), ("tile", ctypes.c_int), ("tiles_per_side", ctypes.c_int),
-                ("stages", ctypes.c_int)]
+                ("stages", ctypes.c_int), ("wide", ctypes.c_int)]
 
 
 KERNEL_NAMES = ("k_diag", "k_tile", "k_between", "k_stage")
@@ -120,6 +120,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "nf_serve_stats": (c_int, [ctypes.POINTER(ServeStats)]),
         "nf_autotune_q": (c_int, [c_int]),
         "nf_autotune_target": (c_int, [c_int, c_int]),
+        "nf_autotune_wide": (c_int, [c_int, c_int]),
         "nf_autotune": (c_int, [c_int, c_int, c_int, c_int]),
         "nf_profile_fold": (c_int, [vp, c_int, c_int, c_int, vp, ctypes.POINTER(KernelProfile)]),
         "nf_lds_gather_rate": (c_int, [c_int, c_int, ctypes.POINTER(ctypes.c_double)]),
@@ -463,6 +464,11 @@ def nf_autotune_target(n: int, q: int = 0) -> int:
     """Between-group chunks per wavefront step of a single fold of length n at
     group width q (0: the q that q = 0 resolves to)."""
     return _check(load().nf_autotune_target(n, q))
+
+
+def nf_autotune_wide(n: int, q: int = 0) -> bool:
+    """Whether a single fold of length n at q runs the wide fused step."""
+    return bool(_check(load().nf_autotune_wide(n, q)))
 
 
 def nf_autotune(n: int, qmin: int = 4, qmax: int = 8, reps: int = 3) -> int:

@@ -175,11 +175,11 @@ def _tuning_in_subprocess(tmp_path, lines, env_extra, lengths):
     import sys
     f = tmp_path / "tune.txt"
     f.write_text("".join(l + "\n" for l in lines))
-    env = {k: v for k, v in os.environ.items() if k != "NF_BETWEEN_TARGET"}
+    env = {k: v for k, v in os.environ.items() if k not in ("NF_BETWEEN_TARGET", "NF_STAGE_WIDE")}
     env.update(NF_AUTOTUNE_CACHE=str(f), **env_extra)
     code = ("import json,sys; sys.path.insert(0, %r); from paper_1307_7820_amd import nf; "
-            "print(json.dumps([[nf.nf_autotune_q(n), nf.nf_autotune_target(n), nf.nf_autotune_target(n, 8)] "
-            "for n in %r]))" % (ROOT, lengths))
+            "print(json.dumps([[nf.nf_autotune_q(n), nf.nf_autotune_target(n), nf.nf_autotune_target(n, 8), "
+            "int(nf.nf_autotune_wide(n, 8))] for n in %r]))" % (ROOT, lengths))
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr
     return json.loads(out.stdout.strip().splitlines()[-1])
@@ -189,16 +189,22 @@ def test_tune_file_sets_q_and_chunk_target_per_bucket(tmp_path):
     # buckets: n < 256 is 0, then one per doubling; 6000 is in bucket 5, 16000 in 6
     lines = ["5 7 256", "6 8", "2 4 0", "9 12 512", "junk", "3 5 2048 extra"]
     # [tuned q, target at that q, target at q = 8]
+    # [tuned q, target at that q, target at q = 8, wide fused step at q = 8]
     got = _tuning_in_subprocess(tmp_path, lines, {}, [6000, 16000, 700, 300, 100])
-    assert got[0] == [7, 256, 1024]   # both columns; the target holds for q = 7 only
-    assert got[1] == [8, 1024, 1024]  # no target column: the default
-    assert got[2] == [4, 1024, 1024]  # target 0: the default
-    assert got[3] == [8, 1024, 1024]  # q = 12 is out of range: the whole line is ignored
-    assert got[4] == [8, 1024, 1024]  # no line for bucket 0
+    assert got[0] == [7, 256, 1024, 0]   # both columns; the target holds for q = 7 only
+    assert got[1] == [8, 1024, 1024, 1]  # no target column: the default; n >= 8192 is wide
+    assert got[2] == [4, 1024, 1024, 0]  # target 0: the default
+    assert got[3] == [8, 1024, 1024, 0]  # q = 12 is out of range: the whole line is ignored
+    assert got[4] == [8, 1024, 1024, 0]  # no line for bucket 0
     got = _tuning_in_subprocess(tmp_path, ["5 8 512"], {}, [6000])
-    assert got == [[8, 512, 512]]
+    assert got == [[8, 512, 512, 0]]
     got = _tuning_in_subprocess(tmp_path, ["5 7 256"], {"NF_BETWEEN_TARGET": "333"}, [6000, 100])
-    assert got == [[7, 333, 333], [8, 333, 333]]  # the environment overrides every target
+    assert got == [[7, 333, 333, 0], [8, 333, 333, 0]]  # the environment overrides every target
+    # the fourth column: the fused-step shape tuned at that q
+    got = _tuning_in_subprocess(tmp_path, ["5 8 256 1", "6 8 1024 0", "7 7 1024 1"], {}, [6000, 16000, 20000])
+    assert got == [[8, 256, 256, 1], [8, 1024, 1024, 0], [7, 1024, 1024, 1]]
+    got = _tuning_in_subprocess(tmp_path, ["6 8 1024 0"], {"NF_STAGE_WIDE": "1"}, [16000, 100])
+    assert [g[3] for g in got] == [1, 1]  # the environment overrides the choice
 
 
 def test_autotune_target_rejects_bad_length(lib):

@@ -74,3 +74,35 @@ def test_repeat_runs_identical(nf_mode):
     assert a == oracle.fold_score(s1)
     assert b == oracle.fold_score(s2)
     assert nf_mode.nf_fold(s1, q=8) == a
+
+
+@pytest.fixture(params=["0", "1"])
+def nf_shape(request):
+    """Both shapes of the fused step (default and wide, q = 8), forced."""
+    from paper_1307_7820_amd import nf as m
+    old = {k: os.environ.get(k) for k in ("NF_STAGE_WIDE", "NF_MODE")}
+    os.environ["NF_STAGE_WIDE"] = request.param
+    os.environ["NF_MODE"] = "fused"
+    m.nf_shutdown()
+    yield m
+    m.nf_shutdown()
+    for k, v in old.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+
+
+def test_fused_step_shapes_equal_the_oracle(nf_shape):
+    wide = os.environ["NF_STAGE_WIDE"] == "1"
+    for k, n in enumerate([2, 63, 64, 65, 255, 257, 700, 1283]):
+        s = gen.iid_sequence(n, [310, k])
+        assert nf_shape.nf_autotune_wide(n, 8) == wide
+        score, T = nf_shape.nf_fold(s, q=8, table=True)
+        assert np.array_equal(T, oracle.fold_table(s)), (n, wide)
+    s = gen.stem_sequence(900, [311])
+    assert np.array_equal(nf_shape.nf_fold(s, q=8, table=True)[1], oracle.fold_table(s))
+    # the headline length in the shape it does not take by default, and back
+    s = gen.workload_n6000()
+    score, T = nf_shape.nf_fold(s, q=8, table=True)
+    assert np.array_equal(T, oracle.fold_table(s)), wide
