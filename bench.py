@@ -276,11 +276,19 @@ def cpu_baseline(seq: str, gen, budget_s: float):
 
 
 def extra_n16000(nf, torch, gen, steps, lds):
+    """The n = 16000 fold with q, the chunk target and the fused-step shape
+    chosen by the autotuner for its length (tuned before the timed region)."""
     seq = gen.workload_n16000()
-    ms, wall, score, codes = time_fold(nf, torch, seq, 8, steps, 1)
+    n = len(seq)
+    t0 = time.perf_counter()
+    q = nf.nf_autotune(n, 4, 8, 2)
+    tune_s = time.perf_counter() - t0
+    ms, wall, score, codes = time_fold(nf, torch, seq, q, steps, 1)
     t = ms / 1e3 / steps
-    r = roofline(nf, codes, len(seq), 8, lds, reps=1)
-    return {"n": 16000, "q": 8, "ms_per_fold": t * 1e3, "gcups": cells(16000) / t / 1e9,
+    r = roofline(nf, codes, n, q, lds, reps=1)
+    return {"n": 16000, "q": q, "between_chunks_per_step": nf.nf_autotune_target(n, q),
+            "wide_fused_step": nf.nf_autotune_wide(n, q), "autotune_s": tune_s,
+            "ms_per_fold": t * 1e3, "gcups": cells(16000) / t / 1e9,
             "split_equivalent_gsps": splits(16000) / t / 1e9,
             "glookups_per_s": r.get("glookups_per_s"), "score": score, "roofline": r}
 
@@ -355,26 +363,39 @@ def extra_structure(nf, gen, reps=3):
 
 
 def extra_batch(nf, torch, gen, lds):
-    """The 4096-sequence batch: one prepared batch (one HIP graph) against the
-    same 4096 folds run one by one with the single-fold call (device codes,
-    every plan made and captured before the timed loop), both timed over all
-    4096 folds."""
+    """The 4096-sequence batch: one prepared batch (q tuned per length bucket,
+    one packed wavefront per q, captured as HIP graphs) against the same 4096
+    folds run one by one with the single-fold call at the same q (device
+    codes, every plan made and captured before the timed loop), both timed
+    over all 4096 folds; and the batch at a fixed q = 8."""
     seqs = gen.workload_batch4096()
-    t0 = time.perf_counter()
-    b = nf.Batch(seqs, q=8)
-    prep = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
-    b.run(stream)
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     reps = 3
-    e0.record(stream)
-    for _ in range(reps):
+
+    def time_batch(b):
         b.run(stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            b.run(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    # q for each length bucket of the batch (n < 256, < 512, < 1024, < 2048),
+    # tuned at one length inside each bucket before the timed region
+    t0 = time.perf_counter()
+    bucket_q = {str(m): nf.nf_autotune(m, 4, 8, 3) for m in (181, 362, 724, 1448)}
+    tune_s = time.perf_counter() - t0
+    b8 = nf.Batch(seqs, q=8)
+    ms_q8 = time_batch(b8)
+    scores_q8 = b8.scores()
+    b8.close()
+    t0 = time.perf_counter()
+    b = nf.Batch(seqs, q=0)
+    prep = time.perf_counter() - t0
+    ms = time_batch(b)
     scores = b.scores()
     # structures of all 4096 folds (nf_batch_structures: one traceback
     # workgroup per fold, host call including the copies)
@@ -387,20 +408,22 @@ def extra_batch(nf, torch, gen, lds):
     cds = [torch.from_numpy(nf.encode(s)).cuda() for s in seqs]
     d_scores = torch.zeros(len(seqs), dtype=torch.int32, device="cuda")
     for i, c in enumerate(cds):  # makes and captures every single-fold plan
-        nf.nf_fold_dev(c, len(seqs[i]), 8, d_scores[i:i + 1], None, stream)
+        nf.nf_fold_dev(c, len(seqs[i]), 0, d_scores[i:i + 1], None, stream)
     torch.cuda.synchronize()
     e0.record(stream)
     for i, c in enumerate(cds):
-        nf.nf_fold_dev(c, len(seqs[i]), 8, d_scores[i:i + 1], None, stream)
+        nf.nf_fold_dev(c, len(seqs[i]), 0, d_scores[i:i + 1], None, stream)
     e1.record(stream)
     torch.cuda.synchronize()
     loop_ms = e0.elapsed_time(e1)
     looped_same = bool(torch.equal(d_scores.cpu(), torch.from_numpy(scores)))
     tot_cells = sum(cells(len(s)) for s in seqs)
-    work = [fold_work(len(s), 8) for s in seqs]
+    work = [fold_work(len(s), nf.nf_autotune_q(len(s))) for s in seqs]
     roof = roofline_times(sum(w[0] for w in work), sum(w[1] for w in work), sum(w[2] for w in work), ms / 1e3,
                           lds["row_gathers_per_s"])
-    return {"count": len(seqs), "ms_per_batch": ms, "folds_per_s": len(seqs) / (ms / 1e3),
+    return {"count": len(seqs), "q": "tuned per length bucket", "bucket_q": bucket_q, "autotune_s": tune_s,
+            "ms_per_batch": ms, "folds_per_s": len(seqs) / (ms / 1e3),
+            "ms_per_batch_q8": ms_q8, "scores_equal_q8": bool((scores == scores_q8).all()),
             "gcups": tot_cells / (ms / 1e3) / 1e9, "prepare_s": prep,
             "looped_ms_all": loop_ms, "looped_folds_per_s": len(seqs) / (loop_ms / 1e3),
             "speedup_vs_looped": loop_ms / ms, "looped_scores_equal_batch": looped_same,

@@ -175,8 +175,10 @@ int nf_fold_dev_noalloc(const uint8_t* d_codes, int n, int q, int32_t* d_score, 
  * Handles are opaque; a handle must only be used from one thread at a time. */
 typedef struct nf_batch nf_batch;
 
-/* seqs[i] holds ns[i] bases (i < count).  q as above (0 = autotuned for the
- * batch's longest sequence). */
+/* seqs[i] holds ns[i] bases (i < count).  q as above; with q = 0 every fold
+ * takes the q tuned for its own length bucket (nf_autotune_q), and the folds
+ * of each q form one packed wavefront of their own: the groups run at once,
+ * on streams forked from and joined back into the stream of nf_batch_run. */
 int nf_batch_create(const char* const* seqs, const int* ns, int count, int q, nf_batch** out);
 /* Enqueue one complete fill of every sequence in the batch on stream. */
 int nf_batch_run(nf_batch* b, void* stream);

@@ -15,15 +15,27 @@ std::recursive_mutex g_api;
 
 }
 
+// A prepared batch: one plan per group width q among its folds (q = 0 gives
+// each fold the q tuned for its length bucket).  Plan k > 0 runs on a stream
+// of its own, forked from and joined back into the caller's stream.
 struct nf_batch {
-    std::unique_ptr<Plan> plan;
+    std::vector<std::unique_ptr<Plan>> plans;
     std::vector<int> ns;
-    hipEvent_t done = nullptr;
+    std::vector<std::pair<int, int>> where;  // fold i -> (plan, index in that plan)
+    std::vector<hipStream_t> side;           // side[k - 1] runs plan k
+    std::vector<hipEvent_t> joins;           // joins[k - 1] marks the end of plan k
+    hipEvent_t fork = nullptr, done = nullptr;
+    DevBuf S, tb;  // expand target for table copies; traceback scratch
     bool ran = false;
     ~nf_batch()
     {
         if (done) (void)hipEventDestroy(done);
+        if (fork) (void)hipEventDestroy(fork);
+        for (auto e : joins) (void)hipEventDestroy(e);
+        for (auto st : side) (void)hipStreamDestroy(st);
     }
+    Plan& plan_of(int i) { return *plans[where[i].first]; }
+    int index_in(int i) const { return where[i].second; }
 };
 
 extern "C" {
@@ -223,11 +235,9 @@ int nf_batch_create(const char* const* seqs, const int* ns, int count, int q, nf
     if (count < 0 || (count > 0 && (!seqs || !ns))) return fail(NF_E_INVAL, "bad batch arguments");
     int rc = check_q(q);
     if (rc) return rc;
-    int nmax = 0;
     for (int i = 0; i < count; ++i) {
         if ((rc = check_length(ns[i]))) return fail(rc, "sequence %d: %s", i, last_error());
         if (!seqs[i] && ns[i] > 0) return fail(NF_E_INVAL, "sequence %d is NULL", i);
-        nmax = std::max(nmax, ns[i]);
     }
     std::vector<std::vector<uint8_t>> codes(count);
     for (int i = 0; i < count; ++i) {
@@ -235,20 +245,49 @@ int nf_batch_create(const char* const* seqs, const int* ns, int count, int q, nf
         if ((rc = encode_sequence(seqs[i], ns[i], codes[i].data()))) return fail(rc, "sequence %d: %s", i, last_error());
     }
     if ((rc = ensure_device())) return rc;
-    q = resolve_q(q, nmax);
     auto b = std::make_unique<nf_batch>();
     b->ns.assign(ns, ns + count);
-    if ((rc = make_plan(b->ns, q, b->plan))) return rc;
-    Plan& p = *b->plan;
+    b->where.resize(count);
+    // the group width of every fold, and one plan per width
+    std::vector<int> qs(count), widths;
+    for (int i = 0; i < count; ++i) {
+        qs[i] = q ? q : resolve_q(0, ns[i]);
+        if (std::find(widths.begin(), widths.end(), qs[i]) == widths.end()) widths.push_back(qs[i]);
+    }
+    std::sort(widths.begin(), widths.end(), [&](int x, int y) { return x > y; });
+    for (size_t k = 0; k < widths.size(); ++k) {
+        std::vector<int> group;
+        for (int i = 0; i < count; ++i)
+            if (qs[i] == widths[k]) {
+                b->where[i] = {(int)k, (int)group.size()};
+                group.push_back(ns[i]);
+            }
+        std::unique_ptr<Plan> p;
+        if ((rc = make_plan(group, widths[k], p))) return rc;
+        b->plans.push_back(std::move(p));
+    }
     // zero-padded codes of every fold; the host buffers live until the copies finish
     hipStream_t s = ctx().stream;
     StreamFence fence{s};
     for (int i = 0; i < count; ++i) {
-        codes[i].resize(p.geom[i].codes_bytes, 0);
-        HIPCHK(hipMemcpyAsync((void*)p.h_folds[i].codes, codes[i].data(), codes[i].size(), hipMemcpyHostToDevice, s));
+        Plan& p = b->plan_of(i);
+        const int k = b->index_in(i);
+        codes[i].resize(p.geom[k].codes_bytes, 0);
+        HIPCHK(hipMemcpyAsync((void*)p.h_folds[k].codes, codes[i].data(), codes[i].size(), hipMemcpyHostToDevice, s));
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+    if (b->plans.size() > 1) {
+        HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+        for (size_t k = 1; k < b->plans.size(); ++k) {
+            hipStream_t st = nullptr;
+            hipEvent_t e = nullptr;
+            HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            b->side.push_back(st);
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            b->joins.push_back(e);
+        }
+    }
     *out = b.release();
     return NF_OK;
 }
@@ -261,7 +300,14 @@ int nf_batch_run(nf_batch* b, void* stream)
     int rc = ensure_device();
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = plan_enqueue(*b->plan, s))) return rc;
+    if (b->plans.size() > 1) HIPCHK(hipEventRecord(b->fork, s));
+    for (size_t k = 1; k < b->plans.size(); ++k) {
+        HIPCHK(hipStreamWaitEvent(b->side[k - 1], b->fork, 0));
+        if ((rc = plan_enqueue(*b->plans[k], b->side[k - 1]))) return rc;
+        HIPCHK(hipEventRecord(b->joins[k - 1], b->side[k - 1]));
+    }
+    if (!b->plans.empty() && (rc = plan_enqueue(*b->plans[0], s))) return rc;
+    for (size_t k = 1; k < b->plans.size(); ++k) HIPCHK(hipStreamWaitEvent(s, b->joins[k - 1], 0));
     HIPCHK(hipEventRecord(b->done, s));
     b->ran = true;
     return NF_OK;
@@ -274,8 +320,14 @@ int nf_batch_scores(nf_batch* b, int32_t* scores_out)
     if (!b || !scores_out) return fail(NF_E_INVAL, "NULL argument");
     if (!b->ran) return fail(NF_E_INVAL, "batch has not been run");
     HIPCHK(hipEventSynchronize(b->done));
-    if (!b->ns.empty())
-        HIPCHK(hipMemcpy(scores_out, b->plan->d_scores.p, b->ns.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<std::vector<int32_t>> per(b->plans.size());
+    for (size_t k = 0; k < b->plans.size(); ++k) {
+        per[k].resize(b->plans[k]->geom.size());
+        if (!per[k].empty())
+            HIPCHK(hipMemcpy(per[k].data(), b->plans[k]->d_scores.p, per[k].size() * sizeof(int32_t),
+                             hipMemcpyDeviceToHost));
+    }
+    for (size_t i = 0; i < b->ns.size(); ++i) scores_out[i] = per[b->where[i].first][b->where[i].second];
     return NF_OK;
 }
 
@@ -290,13 +342,14 @@ int nf_batch_table(nf_batch* b, int idx, int16_t* S_out)
     const int n = b->ns[idx];
     if (n == 0) return NF_OK;
     const size_t bytes = (size_t)n * n * sizeof(int16_t);
-    Plan& p = *b->plan;
+    Plan& p = b->plan_of(idx);
+    const int k = b->index_in(idx);
     int rc;
-    if (p.d_S.bytes < bytes && (rc = p.d_S.alloc(bytes))) return rc;
+    if (b->S.bytes < bytes && (rc = b->S.alloc(bytes))) return rc;
     hipStream_t s = ctx().stream;
     StreamFence fence{s};
-    HIPCHK(launch_expand(p.h_folds[idx].F, p.geom[idx].ld, n, (int16_t*)p.d_S.p, s));
-    HIPCHK(hipMemcpyAsync(S_out, p.d_S.p, bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(launch_expand(p.h_folds[k].F, p.geom[k].ld, n, (int16_t*)b->S.p, s));
+    HIPCHK(hipMemcpyAsync(S_out, b->S.p, bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return NF_OK;
 }
@@ -308,7 +361,6 @@ int nf_batch_structures(nf_batch* b, char* const* db_outs)
     if (!b || !db_outs) return fail(NF_E_INVAL, "NULL argument");
     if (!b->ran) return fail(NF_E_INVAL, "batch has not been run");
     HIPCHK(hipEventSynchronize(b->done));
-    Plan& p = *b->plan;
     const int count = (int)b->ns.size();
     std::vector<int> idx;  // folds that get a structure
     size_t db_total = 0, sp_total = 0;
@@ -327,16 +379,18 @@ int nf_batch_structures(nf_batch* b, char* const* db_outs)
     const size_t sp_off = db_off + up(db_total);
     const size_t bytes = sp_off + sp_total * sizeof(int2);
     int rc;
-    if (p.d_tb.bytes < bytes && (rc = p.d_tb.alloc(bytes))) return rc;
-    char* base = (char*)p.d_tb.p;
+    if (b->tb.bytes < bytes && (rc = b->tb.alloc(bytes))) return rc;
+    char* base = (char*)b->tb.p;
     std::vector<TracebackWork> work(nw);
     size_t dbo = 0, spo = 0;
     for (size_t k = 0; k < nw; ++k) {
         const int i = idx[k], n = b->ns[i];
+        const Plan& p = b->plan_of(i);
+        const int f = b->index_in(i);
         TracebackWork& w = work[k];
-        w.F = p.h_folds[i].F;
-        w.codes = p.h_folds[i].codes;
-        w.ld = p.geom[i].ld;
+        w.F = p.h_folds[f].F;
+        w.codes = p.h_folds[f].codes;
+        w.ld = p.geom[f].ld;
         w.n = n;
         w.spill_cap = n / 2 + 1;
         w.spill = (int2*)(base + sp_off) + spo;
@@ -371,7 +425,11 @@ int nf_batch_info(const nf_batch* b, int* count, size_t* device_bytes)
     clear_error();
     if (!b) return fail(NF_E_INVAL, "batch is NULL");
     if (count) *count = (int)b->ns.size();
-    if (device_bytes) *device_bytes = b->plan->device_bytes;
+    if (device_bytes) {
+        size_t t = b->S.bytes + b->tb.bytes;
+        for (auto& p : b->plans) t += p->device_bytes;
+        *device_bytes = t;
+    }
     return NF_OK;
 }
 

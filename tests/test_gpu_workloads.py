@@ -89,3 +89,50 @@ def test_serving_mix_with_long_band(nf):
         else:
             assert score == oracle.fold_score(s), (k, len(s))
             assert score == nf.nf_fold(s, q=8), (k, len(s))
+
+
+_MIXED_Q_CHILD = r"""
+import json, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_1307_7820_amd import gen, nf
+seqs = gen.batch_sequences(300, 50, 2000, (1307, 44)) + ["", "A", "GC"]
+qs = sorted({nf.nf_autotune_q(len(s)) for s in seqs})
+b = nf.Batch(seqs, q=0)
+b.run()
+got = b.scores()
+bad = [k for k, s in enumerate(seqs) if int(got[k]) != oracle.fold_score(s)]
+tables = 0
+for k in range(0, len(seqs), 23):
+    if seqs[k]:
+        assert np.array_equal(b.table(k), oracle.fold_table(seqs[k])), k
+        tables += 1
+alone = [k for k in range(0, len(seqs), 17) if int(got[k]) != nf.nf_fold(seqs[k], q=nf.nf_autotune_q(len(seqs[k])))]
+dbs = b.structures()
+sbad = [k for k in range(0, len(seqs), 29) if dbs[k] != oracle.structure(seqs[k])]
+print(json.dumps({"qs": qs, "bad": bad, "alone_bad": alone, "tables": tables, "structure_bad": sbad}))
+"""
+
+
+def test_batch_takes_the_tuned_q_of_each_length_bucket(tmp_path):
+    """nf_batch_create(q = 0): each fold takes the q tuned for its length bucket,
+    the folds of each q run as one packed wavefront, and every score, table and
+    structure still equals the oracle's and the fold run alone.  The tune file is
+    read once per process, so the batch runs in a child process of its own."""
+    import json
+    import os
+    import subprocess
+    import sys
+    tune = tmp_path / "tune.txt"
+    tune.write_text("0 5\n1 6\n2 8\n3 4\n")  # n < 256: q 5, < 512: 6, < 1024: 8, < 2048: 4
+    env = dict(os.environ, NF_AUTOTUNE_CACHE=str(tune))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    print("mixed-q batch child", flush=True)
+    out = subprocess.run([sys.executable, "-u", "-c", _MIXED_Q_CHILD, root], env=env, capture_output=True,
+                         text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-3000:]
+    res = json.loads(out.stdout.strip().splitlines()[-1])
+    assert res["qs"] == [4, 5, 6, 8], res
+    assert res["bad"] == [] and res["alone_bad"] == [] and res["structure_bad"] == [], res
+    assert res["tables"] >= 10
