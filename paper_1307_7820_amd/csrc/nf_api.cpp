@@ -7,6 +7,7 @@
 
 #include "nf.h"
 #include "nf_runtime.h"
+#include "nf_test.h"
 
 using namespace nf;
 
@@ -165,6 +166,42 @@ int nf_fold(const char* seq, int n, int q, int16_t* S_out)
         HIPCHK(launch_expand(p->h_folds[0].F, g.ld, n, (int16_t*)p->d_S.p, s));
         HIPCHK(hipMemcpyAsync(S_out, p->d_S.p, bytes, hipMemcpyDeviceToHost, s));
     }
+    HIPCHK(hipStreamSynchronize(s));
+    return score;
+}
+
+int nf_test_set_perturb(unsigned seed)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    perturb_seed() = seed;
+    return NF_OK;
+}
+
+int nf_test_packed_state(const char* seq, int n, int q, uint32_t* rs_out, uint32_t* cs_out, size_t cap_words,
+                         int* nt_out)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_api);
+    clear_error();
+    if (q < 1 || q > NF_Q_MAX) return fail(NF_E_INVAL, "q = %d outside 1..%d", q, NF_Q_MAX);
+    if (n < 2 || !rs_out || !cs_out) return fail(NF_E_INVAL, "needs n >= 2 and both output buffers");
+    int rc = check_length(n);
+    if (rc) return rc;
+    const Geom g0 = make_geom(n, q);
+    if (nt_out) *nt_out = g0.NT;
+    const size_t words = (size_t)tile_count(g0.NT) * state_words(q);
+    if (cap_words < words) return fail(NF_E_INVAL, "packed state needs %zu words per block", words);
+    Plan* p = nullptr;
+    std::vector<uint8_t> padded;
+    int32_t score = 0;
+    StreamFence fence;
+    if ((rc = fill_single(seq, n, q, &p, padded, fence))) return rc;
+    hipStream_t s = ctx().stream;
+    const FoldDesc& f = p->h_folds[0];
+    const size_t skip = (size_t)f.NT * state_words(q);  // the main-diagonal tiles' blocks
+    HIPCHK(hipMemcpyAsync(&score, p->d_scores.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rs_out + skip, f.RS + skip, (words - skip) * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(cs_out + skip, f.CS + skip, (words - skip) * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return score;
 }

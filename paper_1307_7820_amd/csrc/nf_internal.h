@@ -186,6 +186,9 @@ hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uin
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // scores[f] = F(0, n_f)
 hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s);
+// A bounded delay of about iters x 3.4 us (at most 16) on stream s: one wavefront
+// that sleeps (perturbed schedules, nf_test_set_perturb).
+hipError_t launch_delay(int iters, hipStream_t s);
 hipError_t launch_expand(const int16_t* F, int ld, int n, int16_t* S, hipStream_t s);
 // One optimal structure of the fold whose table F (leading dimension ld) and
 // codes are given, as n dot-bracket characters in db; *status = 0 on success.

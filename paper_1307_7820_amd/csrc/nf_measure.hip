@@ -1,3 +1,5 @@
+// Measurement and test kernels outside the fill.
+//
 // nf_lds_gather_rate: the LDS byte-gather ceiling of the device, the unit
 // that bounds a Four-Russians lookup besides VALU issue (one random 1-byte
 // read of R from LDS per lookup, Eq. 3).
@@ -57,7 +59,22 @@ __global__ __launch_bounds__(kGatherThreads) void k_lds_gather(int table_bytes, 
     if (acc == 0x9e3779b9u) sink[0] = acc;  // keeps the reads; practically never true
 }
 
+// One wavefront that sleeps `iters` times for about 8K clocks each: a
+// bounded delay put between the launches of a perturbed schedule.
+__global__ __launch_bounds__(64) void k_delay(int iters)
+{
+    for (int i = 0; i < iters; ++i) __builtin_amdgcn_s_sleep(127);
+}
+
 }  // namespace
+
+hipError_t launch_delay(int iters, hipStream_t s)
+{
+    if (iters <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_delay, dim3(1), dim3(64), 0, s, iters < 16 ? iters : 16);
+    return hipGetLastError();
+}
+
 }  // namespace nf
 
 using namespace nf;

@@ -7,6 +7,7 @@
 #include "nf_runtime.h"
 
 #include <algorithm>
+#include <random>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -500,15 +501,20 @@ int plan_enqueue_direct(Plan& p, hipStream_t s)
     hipEvent_t ev_tile = c.ev_tile, ev_btw = c.ev_btw;
     HIPCHK(hipEventRecord(ev_tile, s));  // fork: s2 starts after the work already on s
     for (int sg = 0; sg < sc.stages; ++sg) {
+        // a perturbed plan delays either stream's launch of this stage by 0..5 sleeps
+        const unsigned h = p.perturb ? (p.perturb * 2654435761u) ^ ((unsigned)sg * 40503u) : 0;
+        const int delay_tile = p.perturb ? (int)((h >> 8) % 6) : 0, delay_btw = p.perturb ? (int)((h >> 16) % 6) : 0;
         if (sg == 0) {
             HIPCHK(launch_diag(p.q, (const TileWork*)p.d_diag.p, (int)sc.diag.size(), s));
         } else {
             HIPCHK(hipStreamWaitEvent(s, ev_btw, 0));  // between(sg-1) done
             HIPCHK(hipEventRecord(ev_tile, s));         // marks finish(sg-1) done
+            HIPCHK(launch_delay(delay_tile, s));
             if (sc.tile_cnt[sg] > 0)
                 HIPCHK(launch_tile(p.q, (const TileWork*)p.d_tile.p + sc.tile_off[sg], sc.tile_cnt[sg], R, s));
         }
         HIPCHK(hipStreamWaitEvent(s2, ev_tile, 0));  // finish(sg-1) done
+        HIPCHK(launch_delay(delay_btw, s2));
         if (sc.btw_cnt[sg] > 0)
             HIPCHK(launch_btw(p, (const BetweenWork*)p.d_btw.p + sc.btw_off[sg], sc.btw_cnt[sg], R, s2));
         HIPCHK(hipEventRecord(ev_btw, s2));
@@ -685,6 +691,7 @@ int make_plan(const std::vector<int>& ns, int q, std::unique_ptr<Plan>& out, int
     p->target = target > 0 ? target : between_target(ns.size() == 1 ? ns[0] : -1, q);
     p->wide = ns.size() == 1 && q == 8 && (wide >= 0 ? wide > 0 : stage_wide(ns[0], q));
     build_schedule(NTs, p->target, p->sc);
+    if ((p->perturb = perturb_seed())) perturb_schedule(p->sc, p->perturb);
     int rc = plan_allocate(*p);
     if (rc) return rc;
     out = std::move(p);
@@ -703,7 +710,8 @@ int single_plan(int n, int q, Plan** out, int target, int wide)
     const int mode_env = !me ? 0 : strcmp(me, "fused") == 0 ? 1 : strcmp(me, "staged") == 0 ? 2 : 0;
     const long long key = (((long long)n * 16 + q) * 2 + (plain_between_for(q) ? 1 : 0)) * 3 + mode_env;
     for (auto it = c.plans.begin(); it != c.plans.end(); ++it) {
-        if (it->first == key && it->second->target == target && it->second->wide == (wide > 0)) {
+        if (it->first == key && it->second->target == target && it->second->wide == (wide > 0) &&
+            it->second->perturb == perturb_seed()) {
             auto ent = std::move(*it);
             c.plans.erase(it);
             c.plans.push_back(std::move(ent));
@@ -730,6 +738,28 @@ int single_plan(int n, int q, Plan** out, int target, int wide)
     c.plans.push_back({key, std::move(p)});
     *out = c.plans.back().second.get();
     return NF_OK;
+}
+
+unsigned& perturb_seed()
+{
+    static unsigned seed = 0;
+    return seed;
+}
+
+// Shuffle the finishes and the between chunks of every wavefront step, and
+// the main-diagonal tiles, in an order drawn from `seed`.  The items of one
+// step touch disjoint cells and packed words, and chunks that share an
+// accumulator slot combine by atomic max, so no order may change a result.
+void perturb_schedule(Schedule& sc, unsigned seed)
+{
+    std::mt19937 rng(seed);
+    std::shuffle(sc.diag.begin(), sc.diag.end(), rng);
+    for (int sg = 0; sg < sc.stages; ++sg) {
+        const auto t0 = sc.tile.begin() + sc.tile_off[sg];
+        const auto b0 = sc.btw.begin() + sc.btw_off[sg];
+        std::shuffle(t0, t0 + sc.tile_cnt[sg], rng);
+        std::shuffle(b0, b0 + sc.btw_cnt[sg], rng);
+    }
 }
 
 int resolve_q(int q, int n)
@@ -882,6 +912,7 @@ std::string check_schedule(const std::vector<int>& NTs, int target)
 {
     Schedule sc;
     build_schedule(NTs, target, sc);
+    if (perturb_seed()) perturb_schedule(sc, perturb_seed());  // the invariants hold in any item order
     char buf[256];
     auto bad = [&](const char* fmt, long long a, long long b, long long c) {
         snprintf(buf, sizeof buf, fmt, a, b, c);
@@ -1018,7 +1049,7 @@ extern "C" int nf_test_schedule(const int* NTs, int count, int target, char* msg
     for (int x : v)
         if (x < 1) return NF_E_INVAL;
     std::string err = nf::check_schedule(v, target);
-    if (err.empty() && count == 1) err = nf::check_single_schedule(v[0], target);
+    if (err.empty() && count == 1 && !nf::perturb_seed()) err = nf::check_single_schedule(v[0], target);
     if (msg && cap > 0) snprintf(msg, (size_t)cap, "%s", err.c_str());
     return err.empty() ? NF_OK : 1;
 }

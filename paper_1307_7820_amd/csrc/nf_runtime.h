@@ -102,6 +102,7 @@ struct Plan {
     bool plain = false;  // between-group work by the plain recurrence (NF_BETWEEN=plain)
     int target = 0;      // between chunks per wavefront step the schedule was built for
     bool wide = false;   // fused steps in the wide shape (three workgroups per CU at q = 8)
+    unsigned perturb = 0;  // test: seed of the shuffled item order and staged delays (0: none)
     std::vector<Geom> geom;
     std::vector<FoldDesc> h_folds;
     Schedule sc;
@@ -147,6 +148,10 @@ int encode_sequence(const char* seq, int n, uint8_t* out);
 int check_length(int n);
 int check_q(int q);
 int resolve_q(int q, int n);
+// Test hook state: the seed plans made from now on perturb their schedule with
+// (nf_test_set_perturb; 0 = none).
+unsigned& perturb_seed();
+void perturb_schedule(Schedule& sc, unsigned seed);
 Geom make_geom(int n, int q);
 void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, int target,
                     std::vector<BetweenItem>& out, int* next_slot,

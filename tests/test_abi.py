@@ -11,8 +11,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "nf.h")
 
 
-def _declared_functions():
-    text = open(HEADER).read()
+def _declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = set(re.findall(r"\b(nf_[A-Za-z_]+)\s*\(", text))
     return sorted(names)
@@ -31,6 +31,10 @@ def test_header_and_binding_agree():
 
 def test_every_declared_symbol_is_exported(lib):
     for name in _declared_functions():
+        assert hasattr(lib, name), name
+    hooks = _declared_functions(os.path.join(ROOT, "include", "nf_test.h"))
+    assert set(hooks) == {"nf_test_schedule", "nf_test_set_perturb", "nf_test_packed_state"}
+    for name in hooks:
         assert hasattr(lib, name), name
 
 
@@ -90,6 +94,37 @@ def test_schedule_invariants_batches(lib):
     from paper_1307_7820_amd import gen
     nts = [(len(s) + 1 + 63) // 64 for s in gen.workload_batch4096()]
     _check_schedule(lib, nts, 1024)
+
+
+def test_schedule_invariants_hold_in_perturbed_order(lib):
+    # the race-detection hook shuffles every step's items; the schedule's
+    # invariants (each tile once, each group tile once, slots disjoint) must
+    # not depend on the order
+    import numpy as np
+    rng = np.random.default_rng([602])
+    try:
+        for seed in (1, 7, 12345):
+            assert lib.nf_test_set_perturb(seed) == 0
+            for nt in [1, 4, 5, 9, 40, 94]:
+                for target in [1, 64, 1024]:
+                    _check_schedule(lib, [nt], target)
+            for t in range(5):
+                nts = [int(x) for x in rng.integers(1, 40, size=int(rng.integers(2, 50)))]
+                _check_schedule(lib, nts, int(rng.choice([5, 100, 1024])))
+    finally:
+        lib.nf_test_set_perturb(0)
+
+
+def test_packed_state_hook_rejects_bad_input(lib):
+    from paper_1307_7820_amd import nf
+    nt = ctypes.c_int(-1)
+    buf = (ctypes.c_uint32 * 8)()
+    assert lib.nf_test_packed_state(b"ACGU", 4, 0, buf, buf, ctypes.c_size_t(8), ctypes.byref(nt)) == nf.NF_E_INVAL
+    assert lib.nf_test_packed_state(b"A", 1, 8, buf, buf, ctypes.c_size_t(8), ctypes.byref(nt)) == nf.NF_E_INVAL
+    assert lib.nf_test_packed_state(b"ACGU", 4, 8, None, buf, ctypes.c_size_t(8), ctypes.byref(nt)) == nf.NF_E_INVAL
+    # n = 100 at q = 8: 64-post tiles, NT = 2, 3 tiles of 8 x 64 words per block
+    assert lib.nf_test_packed_state(b"A" * 100, 100, 8, buf, buf, ctypes.c_size_t(8), ctypes.byref(nt)) == nf.NF_E_INVAL
+    assert nt.value == 2 and "1536 words" in nf.last_error()
 
 
 def test_schedule_hook_rejects_bad_input(lib):

@@ -84,3 +84,15 @@ def test_bad_arguments():
         serial.nf_serial_fold("ACGU", 4, "full_memo", threads=2)
     with pytest.raises(ValueError):
         serial.nf_serial_fold("ACGU", 4, 9)
+
+
+def test_library_exports_every_declared_symbol():
+    import os
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(root, "include", "nf_serial.h")).read(), flags=re.S)
+    names = set(re.findall(r"\b(nf_serial_[A-Za-z_]+)\s*\(", text))
+    assert names == {"nf_serial_fold"}
+    lib = serial.load()
+    for name in names:
+        assert hasattr(lib, name), name
