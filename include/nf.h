@@ -159,7 +159,7 @@ int nf_fold_dev(const uint8_t* d_codes, int n, int q, int32_t* d_score, int16_t*
  * makes kernel launches on `stream` only: no allocation, no host copy, no
  * memset, so it can be captured into a graph.  It always runs the fused
  * wavefront steps with R lookups (NF_MODE and NF_BETWEEN do not apply).
- * A fold whose buffers do not fit the array (n > 3455 at q = 8, n > 3135
+ * A fold whose buffers do not fit the array (n > 3519 at q = 8, n > 3199
  * at q = 4, at the default chunk target) is NF_E_NOMEM, with the bytes it needs in
  * nf_last_error(), before any device work.  Every call on a GPU shares that
  * GPU's array and overwrites what the last call left there: calls that

@@ -62,6 +62,27 @@ __device__ __forceinline__ uint32_t r_index_s(uint32_t rw, uint32_t cw)
     return idx;
 }
 
+// The same with both words in vector registers.
+__device__ __forceinline__ uint32_t r_index_v(uint32_t rw, uint32_t cw)
+{
+    uint32_t idx;
+    __asm__("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:WORD_0"
+            : "=v"(idx)
+            : "v"(rw), "v"(cw));
+    return idx;
+}
+
+// max of a and the low 16 bits of b (as an unsigned number), one VALU
+// instruction (SDWA selects the low half of b).
+__device__ __forceinline__ int max_lo16(int a, uint32_t b)
+{
+    int d;
+    __asm__("v_max_i32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+            : "=v"(d)
+            : "v"(a), "v"(b));
+    return d;
+}
+
 // max of the low 16 bits of a, b and c as unsigned numbers, one VALU
 // instruction (the high halves of the operands are ignored).
 __device__ __forceinline__ uint32_t max3_u16(uint32_t a, uint32_t b, uint32_t c)
@@ -355,6 +376,15 @@ __device__ __forceinline__ int rlookup(const uint8_t* Rl, uint32_t rw, uint32_t 
     return (int)((rw & 0xffffu) + (cw >> 16)) + (int)Rl[(rw >> 16) + (cw & 0xffffu)];
 }
 
+// The Eq. 3 term of a row word and a column word in the low 16 bits of the
+// result (the whole row word is added: the term is one split of a cell, so it
+// stays below 2^15 and nothing carries out of the low half; the high half is
+// not meaningful).  Both words in vector registers.
+__device__ __forceinline__ uint32_t rterm(const uint8_t* Rl, uint32_t rw, uint32_t cw)
+{
+    return rw + (cw >> 16) + (uint32_t)Rl[r_index_v(rw, cw)];
+}
+
 // max of v over the 8 lanes l ^ {8, 16, 32} (lanes 8g + c, g = 0..7)
 __device__ __forceinline__ int max_over_groups(int v)
 {
@@ -413,6 +443,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     constexpr int GPB = kBlockFR ? 8 / Q : 1;  // groups per block
     constexpr bool kStageEdges = Lds::kStageEdges;
     constexpr int NE = kStageEdges ? 2 * G : 1;  // end-tile lookups per row (both edges)
+    static_assert(!kStageEdges || NE > 8, "every row's share of the end-tile groups is at least one");
     constexpr int LS = Lds::kLS;
     Cell* Xs = s.Xs;
     int32_t* Lp = s.Lp;
@@ -599,13 +630,17 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     };
     // one end-tile lookup (edge e, group k: x = e*G + k) for row 8b + g and
     // this lane's column
-    auto edge = [&](int x, int b) { return rlookup<Q>(Rl, EB[x * 64 + 8 * b + g], col_word(x)); };
+    // (low 16 bits of the result, see rterm)
+    auto edge = [&](int x, int b) { return rterm(Rl, EB[x * 64 + 8 * b + g], col_word(x)); };
 
     if constexpr (kStageEdges) {
         // rows of block 7 take their end-tile groups here, the other blocks
-        // inside the row loop
+        // inside the row loop (NE = 2G is even)
+        const uint32_t e0 = edge(0, 7);
+        uint32_t e16 = max3_u16(e0, edge(1, 7), e0);
 #pragma unroll
-        for (int x = 0; x < NE; ++x) acc[7] = max(acc[7], edge(x, 7));
+        for (int x = 2; x < NE; x += 2) e16 = max3_u16(e16, edge(x, 7), edge(x + 1, 7));
+        acc[7] = max_lo16(acc[7], e16);
     } else {
         // q < 4: the end tiles' words are read straight from memory
         for (int e = 0; e < nedge; ++e) {
@@ -661,18 +696,20 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     if (g == 7) Qs[1][j] = acc[7];  // row 63: Q complete (no row below)
     // end-tile row and column words of the share of row (bb, r): groups
     // x = r + 8m of block bb-1, loaded one row step ahead of their use
+    // (erw/erc: this row's, ern/ecn: the next row's, fetched while this row
+    // is closed)
     constexpr int kEPer = (NE + 7) / 8;
-    uint32_t erw[kEPer], erc[kEPer];
-    auto fetch_edges = [&](int bb, int r) {
+    uint32_t erw[kEPer], erc[kEPer], ern[kEPer], ecn[kEPer];
+    auto fetch_edges = [&](int bb, int r, uint32_t (&rw)[kEPer], uint32_t (&cw)[kEPer]) {
 #pragma unroll
         for (int m = 0; m < kEPer; ++m) {
             const int x = r + 8 * m;
             const bool live = bb >= 1 && x < NE;
-            erw[m] = live ? EB[x * 64 + 8 * (bb - 1) + g] : 0u;
-            if constexpr (kLean) erc[m] = live ? EC[x * 64 + j] : 0u;
+            rw[m] = live ? EB[x * 64 + 8 * (bb - 1) + g] : 0u;
+            if constexpr (kLean) cw[m] = live ? EC[x * 64 + j] : 0u;
         }
     };
-    if constexpr (kStageEdges) fetch_edges(7, 7);
+    if constexpr (kStageEdges) fetch_edges(7, 7, erw, erc);
     __syncthreads();
     const unsigned long long gmask = GM[g];
 
@@ -698,23 +735,51 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                 lp[0] = la.x; lp[1] = la.y; lp[2] = la.z; lp[3] = la.w;
                 lp[4] = lb.x; lp[5] = lb.y; lp[6] = lb.z; lp[7] = lb.w;
             }
-            int ev = 0;  // best end-tile term of this row's share (words fetched a row ahead)
+            // The row's chain waits on Q: nothing below is issued before
+            // these reads, the end-tile gathers of this row's share (words
+            // fetched a row ahead) go out next with the next row's words, and
+            // their sums come after the closure (see edge_terms)
+            __builtin_amdgcn_sched_barrier(0);
+            uint32_t rg[kEPer];
             if constexpr (kStageEdges) {
                 if (blk >= 1) {
 #pragma unroll
                     for (int m = 0; m < kEPer; ++m) {
                         const int x = rr + 8 * m;
-                        if (x < NE) ev = max(ev, rlookup<Q>(Rl, erw[m], kLean ? erc[m] : col_word(x)));
+                        rg[m] = x < NE ? (uint32_t)Rl[r_index_v(erw[m], kLean ? erc[m] : col_word(x))] : 0u;
                     }
                 }
-                fetch_edges(rr > 0 ? blk : blk - 1, rr > 0 ? rr - 1 : 7);
+                fetch_edges(rr > 0 ? blk : blk - 1, rr > 0 ? rr - 1 : 7, ern, ecn);
             }
+            __builtin_amdgcn_sched_barrier(0);
+            // the end-tile terms of this row's share into the rows of block
+            // blk-1 (Eq. 3; the term's value in the low 16 bits, see rterm)
+            auto edge_terms = [&] {
+                if constexpr (kStageEdges) {
+                    if (blk >= 1) {
+                        uint32_t ev = 0;
+#pragma unroll
+                        for (int m = 0; m < kEPer; m += 2) {
+                            const int m1 = m + 1 < kEPer ? m + 1 : m;
+                            const int x0 = rr + 8 * m, x1 = rr + 8 * (m + 1);
+                            if (x0 >= NE) continue;  // x0 = rr < 8 < NE when m = 0
+                            const uint32_t t0 = erw[m] + ((kLean ? erc[m] : col_word(x0)) >> 16) + rg[m];
+                            const uint32_t t1 = (m + 1 < kEPer && x1 < NE)
+                                                    ? erw[m1] + ((kLean ? erc[m1] : col_word(x1)) >> 16) + rg[m1]
+                                                    : t0;
+                            ev = max3_u16(m == 0 ? t0 : ev, t0, t1);
+                        }
+                        acc[blk - 1] = max_lo16(acc[blk - 1], ev);
+                    }
+                }
+            };
             int q0 = qa.x;
             if (i < T - 1 && g > 0) q0 = max(q0, (int)((gmask >> i) & 1u) + xl);
             // closure over j' in [8g, 8g+8), then across the 8 lane groups
             int p = max(max(q0 + ureg[0], qa.y + ureg[1]), max(qa.z + ureg[2], qa.w + ureg[3]));
             p = max(p, max(max(qb.x + ureg[4], qb.y + ureg[5]), max(qb.z + ureg[6], qb.w + ureg[7])));
             const int xi = max_over_groups(p);  // X(i, j)
+            __builtin_amdgcn_sched_barrier(0);
             // pushes of row i: into row 8*blk+g (one split; -inf unless the row
             // is above i), or for other q into every row above
             if constexpr (kBlockFR) {
@@ -723,7 +788,9 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
 #pragma unroll
                 for (int b = 0; b <= blk; ++b) acc[b] = max(acc[b], lp[b] + xi);
             }
-            if (blk >= 1) acc[blk - 1] = max(acc[blk - 1], ev);
+            // the last row of a block: the next row (in block blk-1) takes
+            // its Q from acc[blk-1] now, so its end-tile terms go in first
+            if (rr == 0) edge_terms();
             if constexpr (kBlockFR) {
                 if (rr == 0 && blk >= 1) {
                     // block blk finished: its q-groups into every row above it
@@ -743,14 +810,16 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                         const uint4 wb = *reinterpret_cast<const uint4*>(&LW[k * 64 + 8 * g + 4]);
                         const uint32_t ws[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
 #pragma unroll
-                        for (int b = 0; b < blk; ++b) acc[b] = max(acc[b], rlookup<Q>(Rl, ws[b], cw));
+                        for (int b = 0; b < blk; ++b) acc[b] = max_lo16(acc[b], rterm(Rl, ws[b], cw));
                     }
                 }
             }
             // Q of row i-1 for this lane's column (pairing partner X(i, j-1)
             // is the lane to the left; column 8w gets it from its readers)
             if (i >= 1) {
-                const int left = __builtin_amdgcn_update_dpp(kNeg, xi, 0x111, 0xF, 0xF, false);  // row_shr:1
+                // row_shr:1.  Lanes with c = 0 take no left partner, so what
+                // they read does not matter (lanes 0, 16, 32, 48 read 0)
+                const int left = __builtin_amdgcn_mov_dpp(xi, 0x111, 0xF, 0xF, true);
                 const int go = (i - 1) & 7, bo = (i - 1) >> 3;
                 if (g == go) {
                     int qv = acc[bo];
@@ -759,6 +828,14 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                 }
             }
             if (g == 0) Xs[i * 64 + j] = (Cell)xi;
+            if (rr > 0) edge_terms();
+            if constexpr (kStageEdges) {
+#pragma unroll
+                for (int m = 0; m < kEPer; ++m) {
+                    erw[m] = ern[m];
+                    if constexpr (kLean) erc[m] = ecn[m];
+                }
+            }
             __syncthreads();
         }
     }

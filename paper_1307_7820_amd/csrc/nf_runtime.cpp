@@ -254,7 +254,7 @@ void append_between(const std::vector<std::pair<int, int>>& folds_nt, int dd, in
     for (auto& fn : folds_nt)
         if (fn.second > dd) W += (long long)(fn.second - dd) * (dd - 3);
     if (W == 0) return;
-    const long long chunk = std::max<long long>(1, (W + target - 1) / target);
+    const long long chunk = std::max<long long>(kMinChunkTiles, (W + target - 1) / target);
     const int nC = dd - 3;
     const int ns = (int)((nC + chunk - 1) / chunk);
     for (auto& fn : folds_nt) {

@@ -308,7 +308,7 @@ def nf_fold_dev(d_codes, n: int, q: int = 0, d_score=None, d_S=None, stream=None
 
 def nf_fold_dev_noalloc(d_codes, n: int, q: int = 0, d_score=None, d_S=None, stream=None) -> None:
     """nf_fold_dev that allocates nothing: every buffer beyond the arguments
-    lives in the library's static device scratch (n up to 3455 at q = 8).
+    lives in the library's static device scratch (n up to 3519 at q = 8).
     Same argument checks as nf_fold_dev."""
     if n < 0:
         raise ValueError("n must be >= 0")

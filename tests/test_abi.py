@@ -327,10 +327,10 @@ def test_noalloc_schedule_closed_form_and_size_limit(lib):
             arr = (ctypes.c_int * 1)(NT)
             rc = lib.nf_test_schedule(arr, 1, target, msg, 256)
             assert rc == 0, (NT, target, msg.value)
-    rc = lib.nf_fold_dev_noalloc(1, 3456, 8, None, None, None)
+    rc = lib.nf_fold_dev_noalloc(1, 3520, 8, None, None, None)
     assert rc == nf.NF_E_NOMEM and "scratch" in nf.last_error()
-    assert lib.nf_fold_dev_noalloc(1, 3136, 4, None, None, None) == nf.NF_E_NOMEM
+    assert lib.nf_fold_dev_noalloc(1, 3200, 4, None, None, None) == nf.NF_E_NOMEM
     # within the limit the call gets as far as the device, which is absent here
-    assert lib.nf_fold_dev_noalloc(1, 3455, 8, None, None, None) == nf.NF_E_DEVICE
+    assert lib.nf_fold_dev_noalloc(1, 3519, 8, None, None, None) == nf.NF_E_DEVICE
     assert lib.nf_fold_dev_noalloc(None, 10, 8, None, None, None) == nf.NF_E_INVAL
     assert lib.nf_fold_dev_noalloc(1, 10, 10, None, None, None) == nf.NF_E_INVAL
