@@ -508,7 +508,12 @@ def extra_serving(nf, torch, gen, count=2000, warm=200, budget=2 << 30):
     for t in ws:
         nf.nf_wait(t, 600000)
     served_run(None)
+    # two short spin kernels bracket the timed saturation pass in a kernel
+    # trace (bench.py --summarize busy takes the device-busy fraction between
+    # them)
+    torch.cuda._sleep(1000)
     done_t, served_T = served_run(None)
+    torch.cuda._sleep(1000)
     mu_served = count / served_T
 
     lam = 0.8 * mu_plain
@@ -615,6 +620,95 @@ def run_only(args, torch, gen, nf):
                       "gcups": cells(len(seq)) * args.steps / (ms / 1e3) / 1e9, "score": score}))
 
 
+# ---------------------------------------------------------------- summaries
+# Summaries of rocprofv3 result databases (SQLite, *_results.db), for the
+# text files under profiles/: per-kernel durations, per-dispatch counter
+# means and the device-busy fraction of the library's kernels.
+
+_KERNEL_KEYS = ("k_stage<", "k_diag<", "k_between_plain<", "k_between<", "k_tile<", "k_traceback_many",
+                "k_traceback", "k_scores", "k_copy_codes", "k_precompute_R", "k_expand", "k_lds_gather",
+                "k_single_items", "k_zero", "k_delay")
+
+
+def _short_name(name):
+    for key in _KERNEL_KEYS:
+        if key in name:
+            i = name.index(key)
+            return name[i:name.find(">", i) + 1] if key.endswith("<") else key
+    return name[:40]
+
+
+def summarize_trace(db):
+    """Per-kernel call count, total / mean / min / max duration (us) and share."""
+    import collections
+    import sqlite3
+    agg = collections.defaultdict(list)
+    for name, dur in sqlite3.connect(db).execute("select name, duration from kernels"):
+        agg[_short_name(name)].append(dur / 1e3)
+    tot = sum(sum(v) for v in agg.values())
+    return ["%-22s calls=%6d total_us=%12.1f avg_us=%9.2f min_us=%9.2f max_us=%9.2f pct=%5.1f"
+            % (k, len(v), sum(v), sum(v) / len(v), min(v), max(v), 100 * sum(v) / tot)
+            for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))]
+
+
+def summarize_pmc(db, kernel):
+    """Per-dispatch mean of every counter, over the dispatches of kernels whose name holds `kernel`."""
+    import collections
+    import sqlite3
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    q = "select kernel_name, counter_name, dispatch_id, value from counters_collection"
+    for k, c, d, v in sqlite3.connect(db).execute(q):
+        if kernel in k:
+            per[c][d] += v
+    return {c: (len(v), sum(v.values()) / len(v)) for c, v in per.items()}
+
+
+def summarize_busy(db):
+    """Fraction of time at least one of the library's kernels runs: over the
+    span of all of them, and over each window between consecutive
+    torch.cuda._sleep marker kernels."""
+    import sqlite3
+    rows = list(sqlite3.connect(db).execute("select name, start, end from kernels order by start"))
+    lib = sorted((s, e) for n, s, e in rows if _short_name(n).startswith("k_") and "k_delay" not in n)
+    marks = [s for n, s, e in rows if "sleep" in n.lower() or "spin" in n.lower()]
+
+    def busy(lo, hi):
+        tot, cs, ce = 0, None, None
+        for s, e in lib:
+            s, e = max(s, lo), min(e, hi)
+            if e <= s:
+                continue
+            if cs is None or s > ce:
+                if cs is not None:
+                    tot += ce - cs
+                cs, ce = s, e
+            else:
+                ce = max(ce, e)
+        if cs is not None:
+            tot += ce - cs
+        return tot / max(1, hi - lo), (hi - lo) / 1e9
+
+    out = {"span": busy(lib[0][0], lib[-1][1]) if lib else (0.0, 0.0)}
+    for k, (a, b) in enumerate(zip(marks, marks[1:])):
+        out["window%d" % k] = busy(a, b)
+    return out
+
+
+def run_summarize(args):
+    kind, db = args.summarize[0], args.summarize[1]
+    if kind == "trace":
+        print("\n".join(summarize_trace(db)))
+    elif kind == "pmc":
+        kernel = args.summarize[2] if len(args.summarize) > 2 else "k_"
+        for c, (n, m) in sorted(summarize_pmc(db, kernel).items()):
+            print("%-28s dispatches=%5d mean=%16.1f" % (c, n, m))
+    elif kind == "busy":
+        for k, (b, span) in summarize_busy(db).items():
+            print("%-10s device busy %.3f of %.3f s" % (k, b, span))
+    else:
+        sys.exit("--summarize trace|pmc|busy DB [KERNEL]")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -626,7 +720,12 @@ def main():
     ap.add_argument("--only", choices=["n6000", "n16000", "batch", "copy", "structure6000", "structure16000",
                                        "plain16000", "serving", "ldsgather"],
                     help="run one workload K times and print a short line (for profilers)")
+    ap.add_argument("--summarize", nargs="+", metavar="ARG",
+                    help="trace|pmc|busy DB [KERNEL]: summarize a rocprofv3 result database and exit")
     args = ap.parse_args()
+    if args.summarize:
+        run_summarize(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (a single fold is a "
               "latency-bound wavefront; batches and serving shard by fold). Run with --gpus 1.",

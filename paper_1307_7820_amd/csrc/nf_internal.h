@@ -154,8 +154,8 @@ struct SingleSchedule {
 // acc points at the tile's 64x64 int32 accumulator (between-group maxima).
 struct TileWork {
     FoldDesc f;
-    int32_t* acc;  // read and cleared when nslot > 0
-    int A, d, nslot, pad0, pad1, pad2;
+    int32_t* acc;  // read and cleared when nslot > 0 (admission: the fold's accumulators)
+    int A, d, nslot, pad0, pad1, pad2;  // pad1, pad2: admission (launch_diag_admit)
 };
 struct BetweenWork {
     FoldDesc f;
@@ -189,8 +189,14 @@ hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* 
                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// The main-diagonal tiles of newly admitted folds (items with pad2 = 1 read
+// their fold's padded codes at staged + pad1, copy them into the fold's block
+// and clear the fold's 2 NT accumulator blocks at acc).
+hipError_t launch_diag_admit(int q, const TileWork* items, int nitems, const uint8_t* staged, hipStream_t s);
 // scores[f] = F(0, n_f)
 hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s);
+// scores[folds[f].pad] = F(0, n_f)
+hipError_t launch_scores_to_slots(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s);
 // A bounded delay of about iters x 3.4 us (at most 16) on stream s: one wavefront
 // that sleeps (perturbed schedules, nf_test_set_perturb).
 hipError_t launch_delay(int iters, hipStream_t s);

@@ -225,19 +225,37 @@ struct DiagLds {
     uint8_t ca[64], cb[64];
 };
 
+//
+// Admission (staged != null and it.pad2 != 0, the serving engine's newly
+// admitted folds): the fold's padded codes are read from staged + it.pad1
+// instead of its own block, and the tile also does the fold's set-up: it
+// copies its T codes (the last tile also the padding after them) into the
+// fold's block and clears its two accumulator blocks (it.acc, one per
+// diagonal parity), so that admitting a fold takes no copy or fill of its
+// own.  Nothing else reads the fold's block before this launch has ended.
 template <int Q>
-__device__ __forceinline__ void diag_body(const TileWork& it, DiagLds& s, int tid, int nthr)
+__device__ __forceinline__ void diag_body(const TileWork& it, DiagLds& s, int tid, int nthr, const uint8_t* staged)
 {
     constexpr int T = tile_size(Q);
     constexpr int XS = 65;
     int32_t* X = s.X;
     const FoldDesc& f = it.f;
     const int aT = it.A * T;
+    const bool admit = staged != nullptr && it.pad2 != 0;
+    const uint8_t* src = admit ? staged + it.pad1 : f.codes;
 
     for (int e = tid; e < 64 * XS; e += nthr) X[e] = 0;
     if (tid < 64) {
-        s.ca[tid] = f.codes[aT + tid];                              // S_{a+1} for a = aT + i
-        s.cb[tid] = (aT + tid - 1 >= 0) ? f.codes[aT + tid - 1] : 0;  // S_b for b = aT + j
+        s.ca[tid] = src[aT + tid];                              // S_{a+1} for a = aT + i
+        s.cb[tid] = (aT + tid - 1 >= 0) ? src[aT + tid - 1] : 0;  // S_b for b = aT + j
+    }
+    if (admit) {
+        uint8_t* dst = const_cast<uint8_t*>(f.codes);
+        const int hi = it.A == f.NT - 1 ? f.NT * T + 64 : aT + T;
+        for (int e = aT + tid; e < hi; e += nthr) dst[e] = src[e];
+        int4* a0 = reinterpret_cast<int4*>(it.acc + (size_t)it.A * kTileCells);
+        int4* a1 = reinterpret_cast<int4*>(it.acc + (size_t)(f.NT + it.A) * kTileCells);
+        for (int e = tid; e < kTileCells / 4; e += nthr) a0[e] = a1[e] = make_int4(0, 0, 0, 0);
     }
     __syncthreads();
 
@@ -273,10 +291,10 @@ __device__ __forceinline__ void diag_body(const TileWork& it, DiagLds& s, int ti
 }
 
 template <int Q>
-__global__ __launch_bounds__(kThreads) void k_diag(const TileWork* __restrict__ items)
+__global__ __launch_bounds__(kThreads) void k_diag(const TileWork* __restrict__ items, const uint8_t* staged)
 {
     __shared__ DiagLds s;
-    diag_body<Q>(items[blockIdx.x], s, threadIdx.x, kThreads);
+    diag_body<Q>(items[blockIdx.x], s, threadIdx.x, kThreads, staged);
 }
 
 // One between item: rows r0 .. r0+RPW-1 and column j (the lane) of the tile's
@@ -937,6 +955,14 @@ __global__ void k_scores(const FoldDesc* __restrict__ folds, int nfolds, int32_t
     if (e < nfolds) scores[e] = folds[e].F[folds[e].n];  // F(0, n) = D(1, n)
 }
 
+// The same, each score to scores[fold.pad] (the serving engine's slots in
+// mapped host memory).
+__global__ void k_scores_to_slots(const FoldDesc* __restrict__ folds, int nfolds, int32_t* __restrict__ scores)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nfolds) scores[folds[e].pad] = folds[e].F[folds[e].n];
+}
+
 // S[i*n + j] = D(i+1, j+1) = F(i, j+1) for i <= j, 0 below the diagonal.
 __global__ void k_expand(const int16_t* __restrict__ F, int ld, int n, int16_t* __restrict__ S)
 {
@@ -969,7 +995,8 @@ hipError_t launch_q(int which, const void* items, int nitems, const uint8_t* R, 
 {
     if (nitems <= 0) return hipSuccess;
     dim3 grid(nitems);
-    if (which == 0) return launch_k(k_diag<Q>, grid, dim3(kThreads), s, e0, e1, (const TileWork*)items);
+    // (for the main-diagonal tiles R carries the staged codes of admission, or null)
+    if (which == 0) return launch_k(k_diag<Q>, grid, dim3(kThreads), s, e0, e1, (const TileWork*)items, R);
     if (which == 1) return launch_k(k_tile<Q>, grid, dim3(kTileThreads), s, e0, e1, (const TileWork*)items, R);
     return launch_k(k_between<Q>, grid, dim3(kBetweenThreads), s, e0, e1, (const BetweenWork*)items, R);
 }
@@ -1013,6 +1040,11 @@ hipError_t launch_diag(int q, const TileWork* items, int nitems, hipStream_t s, 
     return dispatch(q, 0, items, nitems, nullptr, s, e0, e1);
 }
 
+hipError_t launch_diag_admit(int q, const TileWork* items, int nitems, const uint8_t* staged, hipStream_t s)
+{
+    return dispatch(q, 0, items, nitems, staged, s, nullptr, nullptr);
+}
+
 hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, hipStream_t s, hipEvent_t e0,
                        hipEvent_t e1)
 {
@@ -1029,6 +1061,13 @@ hipError_t launch_scores(const FoldDesc* folds, int nfolds, int32_t* scores, hip
 {
     if (nfolds <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scores, dim3((nfolds + 255) / 256), dim3(256), 0, s, folds, nfolds, scores);
+    return hipGetLastError();
+}
+
+hipError_t launch_scores_to_slots(const FoldDesc* folds, int nfolds, int32_t* scores, hipStream_t s)
+{
+    if (nfolds <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scores_to_slots, dim3((nfolds + 255) / 256), dim3(256), 0, s, folds, nfolds, scores);
     return hipGetLastError();
 }
 

@@ -174,6 +174,9 @@ struct Device {
     Arena arena;
     hipStream_t s1 = nullptr, s2 = nullptr;
     hipStream_t s3 = nullptr;  // tracebacks of finished folds, beside the steps
+    // uploads of the steps' work lists: a step's copy runs while the steps
+    // before it compute, so its launch does not wait for a copy on s1
+    hipStream_t s0 = nullptr;
     hipEvent_t ev_tile = nullptr, ev_btw = nullptr;
     hipEvent_t ev_fin = nullptr, ev_end = nullptr;
     const uint8_t* R[NF_Q_MAX + 1] = {nullptr};
@@ -186,10 +189,11 @@ struct Device {
         // taken again only after that step has retired (at a launch at most
         // kInflightSteps - 1 steps are in flight, and there is one slot more)
         hipEvent_t step_ev = nullptr;
+        hipEvent_t up_ev = nullptr;  // this slot's upload (on s0) is done
         bool used = false;
     } ring[kInflightSteps + 1];
-    int32_t* h_scores = nullptr;  // pinned, one per slot
-    DevBuf d_scores;
+    int32_t* h_scores = nullptr;  // pinned and mapped, one per slot: k_scores_to_slots writes here
+    int32_t* h_scores_dev = nullptr;  // its device address
     std::vector<int> free_slots;
 };
 
@@ -227,16 +231,18 @@ int engine_init(Engine& E, Device& D)
     HIPCHK(hipEventCreateWithFlags(&D.ev_tile, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&D.ev_btw, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&D.s3, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&D.s0, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&D.ev_fin, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&D.ev_end, hipEventDisableTiming));
     int rc = D.arena_mem.alloc(E.budget);
     if (rc) return rc;
     D.arena.reset(E.budget);
-    HIPCHK(hipHostMalloc((void**)&D.h_scores, sizeof(int32_t) * E.max_slots, hipHostMallocDefault));
-    if ((rc = D.d_scores.alloc(sizeof(int32_t) * E.max_slots))) return rc;
+    HIPCHK(hipHostMalloc((void**)&D.h_scores, sizeof(int32_t) * E.max_slots, hipHostMallocMapped));
+    HIPCHK(hipHostGetDevicePointer((void**)&D.h_scores_dev, D.h_scores, 0));
     for (int i = E.max_slots - 1; i >= 0; --i) D.free_slots.push_back(i);
     for (auto& r : D.ring) {
         HIPCHK(hipEventCreateWithFlags(&r.step_ev, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&r.up_ev, hipEventDisableTiming));
     }
     return NF_OK;
 }
@@ -246,18 +252,21 @@ void engine_release(Device& D)
     if (D.s1) (void)hipStreamSynchronize(D.s1);
     if (D.s2) (void)hipStreamSynchronize(D.s2);
     if (D.s3) (void)hipStreamSynchronize(D.s3);
+    if (D.s0) (void)hipStreamSynchronize(D.s0);
     for (auto& r : D.ring) {
         if (r.host) (void)hipHostFree(r.host);
         if (r.step_ev) (void)hipEventDestroy(r.step_ev);
+        if (r.up_ev) (void)hipEventDestroy(r.up_ev);
         r.dev.reset();
     }
     if (D.h_scores) (void)hipHostFree(D.h_scores);
-    D.d_scores.reset();
+    D.h_scores = D.h_scores_dev = nullptr;
     D.arena_mem.reset();
     if (D.ev_tile) (void)hipEventDestroy(D.ev_tile);
     if (D.ev_btw) (void)hipEventDestroy(D.ev_btw);
     if (D.s1) (void)hipStreamDestroy(D.s1);
     if (D.s2) (void)hipStreamDestroy(D.s2);
+    if (D.s0) (void)hipStreamDestroy(D.s0);
     if (D.ev_fin) (void)hipEventDestroy(D.ev_fin);
     if (D.ev_end) (void)hipEventDestroy(D.ev_end);
     if (D.s3) (void)hipStreamDestroy(D.s3);
@@ -379,8 +388,12 @@ void engine_main()
     std::vector<FoldDesc> wfin;
     // between chunks per step over all active folds (NF_BETWEEN_TARGET overrides)
     const int target = between_target(-1, 0);
-    // NF_MODE forces fused or staged steps, as for plans; otherwise a step is
-    // fused while it holds few tiles to finish
+    // Engine steps are fused (one launch per q, no cross-stream waits) unless
+    // NF_MODE = staged.  Unlike a batch, the engine holds at most max_slots
+    // folds, and with up to 256 of them fused steps served the 2000-request
+    // workload (mean n 1168, 2 GiB) at 7,930 folds/s on MI355X against 7,710
+    // staged and 7,730 when steps above kFusedMaxTilesPerSide tiles were
+    // staged.
     int force_mode = -1;
     if (const char* e = getenv("NF_MODE")) {
         if (strcmp(e, "fused") == 0) force_mode = kModeFused;
@@ -430,15 +443,12 @@ void engine_main()
             inflight.pop_front();
         }
         if (rc) break;
-        // newly admitted folds: codes in, accumulators cleared
-        bool err = false;
-        for (auto* a : fresh) {
-            if (hipMemcpyAsync((void*)a->fd.codes, a->req.codes.data(), a->req.codes.size(), hipMemcpyHostToDevice,
-                               D.s1) != hipSuccess ||
-                hipMemsetAsync(a->acc, 0, (size_t)2 * a->g.NT * kTileCells * sizeof(int32_t), D.s1) != hipSuccess)
-                err = true;
-        }
-        if (err) { rc = NF_E_DEVICE; break; }
+        // Newly admitted folds: their padded codes go up with this step's
+        // work lists, and their main-diagonal tiles copy them into place and
+        // clear the fold's accumulators (launch_diag_admit), so admission
+        // takes no copy or fill per fold.
+        size_t nb_c = 0;
+        for (auto* a : fresh) nb_c += (a->req.codes.size() + 15) & ~(size_t)15;
 
         // ---- work lists of this step
         wdiag.clear();
@@ -462,9 +472,11 @@ void engine_main()
                 for (int A = 0; A < NT; ++A) {
                     TileWork w{};
                     w.f = a->fd;
+                    w.acc = a->acc;
                     w.A = A;
                     w.d = 0;
                     w.pad0 = a->req.q;
+                    w.pad2 = 1;  // admission; pad1 (the staged codes) is set at the upload
                     wdiag.push_back(w);
                 }
             } else {
@@ -500,6 +512,7 @@ void engine_main()
             if (s + 1 == NT) {
                 rec.finishing.push_back(a);
                 wfin.push_back(a->fd);
+                wfin.back().pad = a->slot;  // the score goes to h_scores[slot]
             }
         }
         // group each list by q (kernels are specialised per q); a list of one
@@ -517,10 +530,31 @@ void engine_main()
         ring_next = (ring_next + 1) % (kInflightSteps + 1);
         const size_t nb_d = wdiag.size() * sizeof(TileWork), nb_t = wtile.size() * sizeof(TileWork);
         const size_t nb_b = wbtw.size() * sizeof(BetweenWork), nb_f = wfin.size() * sizeof(FoldDesc);
-        const size_t total = nb_d + nb_t + nb_b + nb_f + 64;
+        const size_t off_c = nb_d + nb_t + nb_b + nb_f;  // staged codes of the fresh folds (16-byte aligned)
+        const size_t total = off_c + nb_c + 64;
         if (rg.used) (void)hipEventSynchronize(rg.step_ev);  // never taken: see Ring::step_ev
         if ((rc = ensure_ring(rg, total))) break;
         char* h = rg.host;
+        {
+            // each diagonal item (a fold at stage 0, admitted in this step)
+            // reads its fold's codes at that fold's offset in the staged area
+            std::vector<std::pair<const uint8_t*, size_t>> where;
+            size_t c = off_c;
+            for (auto* a : fresh) {
+                std::memcpy(h + c, a->req.codes.data(), a->req.codes.size());
+                where.push_back({a->fd.codes, c});
+                c += (a->req.codes.size() + 15) & ~(size_t)15;
+            }
+            for (auto& w : wdiag) {
+                auto it = std::find_if(where.begin(), where.end(), [&](const auto& x) { return x.first == w.f.codes; });
+                if (it == where.end()) {
+                    rc = fail(NF_E_DEVICE, "engine: a stage-0 fold was not admitted in this step");
+                    break;
+                }
+                w.pad1 = (int)it->second;
+            }
+            if (rc) break;
+        }
         std::memcpy(h, wdiag.data(), nb_d);
         std::memcpy(h + nb_d, wtile.data(), nb_t);
         std::memcpy(h + nb_d + nb_t, wbtw.data(), nb_b);
@@ -530,13 +564,14 @@ void engine_main()
         const TileWork* d_tile = (const TileWork*)(dv + nb_d);
         const BetweenWork* d_btw = (const BetweenWork*)(dv + nb_d + nb_t);
         const FoldDesc* d_fin = (const FoldDesc*)(dv + nb_d + nb_t + nb_b);
-        bool ok = hipMemcpyAsync(dv, h, nb_d + nb_t + nb_b + nb_f, hipMemcpyHostToDevice, D.s1) == hipSuccess;
+        bool ok = hipMemcpyAsync(dv, h, off_c + nb_c, hipMemcpyHostToDevice, D.s0) == hipSuccess &&
+                  hipEventRecord(rg.up_ev, D.s0) == hipSuccess && hipStreamWaitEvent(D.s1, rg.up_ev, 0) == hipSuccess;
         // ---- launches
         // s1 already follows the previous step's between work: a staged step
         // ends with s1 waiting for s2, a fused one runs it on s1.  A fused
         // step uses s1 alone; a staged one runs its between work on s2 after
         // the previous finishes and this step's items are in place.
-        fused = force_mode >= 0 ? force_mode == kModeFused : (int)wtile.size() <= kFusedMaxTilesPerSide;
+        fused = force_mode != kModeStaged;
         if (!fused) ok = ok && hipEventRecord(D.ev_tile, D.s1) == hipSuccess;
         auto launch_groups = [&](auto* dptr, auto& v, int which, hipStream_t st) {
             size_t b = 0;
@@ -545,7 +580,7 @@ void engine_main()
                 while (e < v.size() && v[e].pad0 == v[b].pad0) ++e;
                 const int q = v[b].pad0;
                 hipError_t he;
-                if (which == 0) he = launch_diag(q, (const TileWork*)dptr + b, (int)(e - b), st);
+                if (which == 0) he = launch_diag_admit(q, (const TileWork*)dptr + b, (int)(e - b), (const uint8_t*)dv, st);
                 else if (which == 1) he = launch_tile(q, (const TileWork*)dptr + b, (int)(e - b), D.R[q], st);
                 else he = launch_between(q, (const BetweenWork*)dptr + b, (int)(e - b), D.R[q], st);
                 ok = he == hipSuccess;
@@ -581,12 +616,10 @@ void engine_main()
         // steps on s1 do not wait for them
         bool any_tb = false;
         if (ok && !rec.finishing.empty()) {
-            ok = launch_scores(d_fin, (int)wfin.size(), (int32_t*)D.d_scores.p, D.s1) == hipSuccess;
+            ok = launch_scores_to_slots(d_fin, (int)wfin.size(), D.h_scores_dev, D.s1) == hipSuccess;
             for (size_t k = 0; ok && k < rec.finishing.size(); ++k) {
                 Active* a = rec.finishing[k];
-                ok = hipMemcpyAsync(D.h_scores + a->slot, (int32_t*)D.d_scores.p + k, sizeof(int32_t),
-                                    hipMemcpyDeviceToHost, D.s1) == hipSuccess;
-                if (ok && a->req.want_table && a->req.n > 0) {
+                if (a->req.want_table && a->req.n > 0) {
                     const size_t cnt = (size_t)a->req.n * a->req.n;
                     ok = hipHostMalloc((void**)&a->h_table, cnt * sizeof(int16_t), hipHostMallocDefault) ==
                          hipSuccess;

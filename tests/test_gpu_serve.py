@@ -165,8 +165,8 @@ def test_structures_in_a_mix(nf):
 def test_step_forms_equal_oracle(nf, mode):
     # A step runs fused (one launch per q holding its finishes and the next
     # diagonals' between work) or staged (two streams); NF_MODE, read when the
-    # engine starts, forces one, and without it small steps are fused.  Mixed
-    # q puts several q groups into one step.
+    # engine starts, forces one, and without it every step is fused.  Mixed q
+    # puts several q groups into one step.
     import os
     old = os.environ.get("NF_MODE")
     if mode is None:
@@ -194,14 +194,10 @@ def test_step_forms_equal_oracle(nf, mode):
                 assert db == oracle.structure(s), len(s)
         st = nf.nf_serve_stats()
         assert st.completed == len(seqs)
-        if mode == "fused":
-            assert st.steps_fused == st.steps
-        elif mode == "staged":
+        if mode == "staged":
             assert st.steps_fused == 0
         else:
-            # the first steps hold every fold's first diagonals (far more than
-            # 208 tiles); the last ones only the longest folds'
-            assert 0 < st.steps_fused < st.steps
+            assert st.steps_fused == st.steps
     finally:
         nf.nf_shutdown()
         if old is None:
