@@ -185,8 +185,9 @@ hipError_t launch_copy_codes(const uint8_t* src, int n, uint8_t* dst, int padded
 // With events e0/e1 the dispatch records the kernel's own start and end.
 hipError_t launch_diag(int q, const TileWork* items, int nitems, hipStream_t s, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
+// wide (q = 8 only): the lean finish, three workgroups per CU
 hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, hipStream_t s,
-                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, bool wide = false);
 hipError_t launch_between(int q, const BetweenWork* items, int nitems, const uint8_t* R, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // The main-diagonal tiles of newly admitted folds (items with pad2 = 1 read

@@ -902,14 +902,19 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     }
 }
 
-template <int Q>
-__global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restrict__ items,
-                                                       const uint8_t* __restrict__ Rg)
+template <int Q, bool kWide>
+constexpr int kStageWavesPerSimd = (Q == 8 && kWide) ? 6 : 1;
+
+// Tile finishes alone (staged steps).  kWide: the lean finish at six
+// wavefronts per SIMD, three workgroups per CU (q = 8), as in the fused step.
+template <int Q, bool kWide>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(kStageWavesPerSimd<Q, kWide>)))
+void k_tile(const TileWork* __restrict__ items, const uint8_t* __restrict__ Rg)
 {
     constexpr int RSZ = 1 << (2 * (Q - 1));
     __shared__ __align__(16) uint8_t Rl[RSZ < 16 ? 16 : RSZ];
-    __shared__ __align__(16) TileLds<Q, false> s;
-    tile_body<Q, true, false>(items[blockIdx.x], Rl, Rg, s, [] {}, [] {});
+    __shared__ __align__(16) TileLds<Q, kWide> s;
+    tile_body<Q, true, kWide>(items[blockIdx.x], Rl, Rg, s, [] {}, [] {});
 }
 
 // One wavefront step in one launch: workgroups [0, ntile) finish the tiles
@@ -924,9 +929,6 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const TileWork* __restric
 // wavefronts per SIMD: the between chunks, which bound long folds, then run
 // faster while each finish runs slower.  (Measured on MI355X: n = 16000
 // 13.2 -> 12.2 ms, n = 6000 2.21 -> 2.34 ms.)
-template <int Q, bool kWide>
-constexpr int kStageWavesPerSimd = (Q == 8 && kWide) ? 6 : 1;
-
 template <int Q, bool kWide>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(kStageWavesPerSimd<Q, kWide>)))
 void k_stage(const TileWork* __restrict__ titems, int ntile,
@@ -997,7 +999,7 @@ hipError_t launch_q(int which, const void* items, int nitems, const uint8_t* R, 
     dim3 grid(nitems);
     // (for the main-diagonal tiles R carries the staged codes of admission, or null)
     if (which == 0) return launch_k(k_diag<Q>, grid, dim3(kThreads), s, e0, e1, (const TileWork*)items, R);
-    if (which == 1) return launch_k(k_tile<Q>, grid, dim3(kTileThreads), s, e0, e1, (const TileWork*)items, R);
+    if (which == 1) return launch_k(k_tile<Q, false>, grid, dim3(kTileThreads), s, e0, e1, (const TileWork*)items, R);
     return launch_k(k_between<Q>, grid, dim3(kBetweenThreads), s, e0, e1, (const BetweenWork*)items, R);
 }
 
@@ -1046,8 +1048,10 @@ hipError_t launch_diag_admit(int q, const TileWork* items, int nitems, const uin
 }
 
 hipError_t launch_tile(int q, const TileWork* items, int nitems, const uint8_t* R, hipStream_t s, hipEvent_t e0,
-                       hipEvent_t e1)
+                       hipEvent_t e1, bool wide)
 {
+    if (wide && q == 8 && nitems > 0)
+        return launch_k(k_tile<8, true>, dim3(nitems), dim3(kTileThreads), s, e0, e1, items, R);
     return dispatch(q, 1, items, nitems, R, s, e0, e1);
 }
 

@@ -103,6 +103,7 @@ struct Plan {
     int target = 0;      // between chunks per wavefront step the schedule was built for
     bool wide = false;   // fused steps in the wide shape (three workgroups per CU at q = 8)
     unsigned perturb = 0;  // test: seed of the shuffled item order and staged delays (0: none)
+    bool tile_wide = false;  // staged finishes in the lean shape (three workgroups per CU at q = 8)
     std::vector<Geom> geom;
     std::vector<FoldDesc> h_folds;
     Schedule sc;

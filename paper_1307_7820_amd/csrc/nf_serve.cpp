@@ -581,7 +581,8 @@ void engine_main()
                 const int q = v[b].pad0;
                 hipError_t he;
                 if (which == 0) he = launch_diag_admit(q, (const TileWork*)dptr + b, (int)(e - b), (const uint8_t*)dv, st);
-                else if (which == 1) he = launch_tile(q, (const TileWork*)dptr + b, (int)(e - b), D.R[q], st);
+                else if (which == 1)
+                    he = launch_tile(q, (const TileWork*)dptr + b, (int)(e - b), D.R[q], st, nullptr, nullptr, true);
                 else he = launch_between(q, (const BetweenWork*)dptr + b, (int)(e - b), D.R[q], st);
                 ok = he == hipSuccess;
                 b = e;
