@@ -40,7 +40,7 @@
 
 namespace nf {
 
-constexpr int kThreads = 256;  // main-diagonal tiles: 4 wavefronts of 64 per workgroup
+constexpr int kThreads = 512;  // main-diagonal tiles: 8 wavefronts, 64 groups of 8 lanes (one pass per diagonal)
 // between-group chunks: 8 wavefronts.  A wavefront owns 16 rows (8 rows
 // measured slower: twice the column-word loads for the same lookups); two
 // wavefronts share each block of rows and take alternate groups of split
