@@ -89,37 +89,37 @@ def kernels_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_bytes(kernel: str, q: int, n: int, target: int):
+def traffic_bytes(kernel: str, q: int, n: int, target: int, wide: int):
     """HBM bytes per launch of `kernel`, from the committed rocprofv3 counter
     summary profiles/<kernel>_q<q>_<workload>_pmc.txt: FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch, separate runs), each scaled by what the same
-    counter reads for a plain device copy of known size.  None when there is
-    no summary for this kernel and workload, when the kernel source has
-    changed since the counters were taken (its hash is in the summary), or
-    when the counters were taken at another number of between-group chunks
-    per step than `target`."""
+    counter reads for a plain device copy of known size.  The summary holds
+    one `traffic:` line per launch configuration measured; the one taken at
+    `target` between-group chunks per step and step shape `wide` (split
+    chunks write by atomic max, so the chunks change the bytes) is used.
+    None when there is no summary or no such line, or when the kernel source
+    has changed since the counters were taken (its hash is in the line)."""
     wl = WORKLOAD_NAMES.get(n)
     if wl is None:
         return None
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "%s_q%d_%s_pmc.txt" % (kernel, q, wl))
     if not os.path.exists(path):
         return None
-    vals = {}
     with open(path) as fh:
         for line in fh:
-            if line.startswith("traffic:"):
-                for kv in line.split()[1:]:
-                    key, _, v = kv.partition("=")
-                    vals[key] = v
-    try:
-        if vals.get("kernels_sha256") != kernels_source_hash():
-            return None
-        if int(vals.get("target", "0")) != target:
-            return None
-        return 1024.0 * (float(vals["fetch_kib"]) * float(vals["fetch_scale"]) +
-                         float(vals["write_kib"]) * float(vals["write_scale"]))
-    except (KeyError, ValueError):
-        return None
+            if not line.startswith("traffic:"):
+                continue
+            vals = dict(kv.partition("=")[::2] for kv in line.split()[1:])
+            try:
+                if vals.get("kernels_sha256") != kernels_source_hash():
+                    continue
+                if int(vals.get("target", "0")) != target or int(vals.get("wide", "0")) != int(wide):
+                    continue
+                return 1024.0 * (float(vals["fetch_kib"]) * float(vals["fetch_scale"]) +
+                                 float(vals["write_kib"]) * float(vals["write_scale"]))
+            except (KeyError, ValueError):
+                continue
+    return None
 
 
 def lds_ceiling(nf, q: int):
@@ -175,7 +175,7 @@ def roofline(nf, codes, n, q, lds, reps=3):
     X = prof.splits[k] / prof.launches[k]
     C = prof.cells[k] / prof.launches[k]
     r = roofline_times(L, X, C, per_launch_s, lds["row_gathers_per_s"])
-    traffic = traffic_bytes(name, q, n, target)
+    traffic = traffic_bytes(name, q, n, target, prof.wide)
     out = {"kernel": name, "launches_per_fold": prof.launches[k] // reps,
            "avg_launch_us": 1e6 * per_launch_s,
            "per_kernel_ms_per_fold": {nf.KERNEL_NAMES[i]: prof.ms[i] / reps for i in ks},
@@ -185,7 +185,7 @@ def roofline(nf, codes, n, q, lds, reps=3):
            "traffic": traffic,
            "hbm_achieved_gbs": traffic / per_launch_s / 1e9 if traffic else None,
            "hbm_frac": traffic / per_launch_s / PEAK_HBM if traffic else None,
-           "q": prof.q, "tile": prof.tile, "between_chunks_per_step": target,
+           "q": prof.q, "tile": prof.tile, "between_chunks_per_step": target, "wide_fused_step": bool(prof.wide),
            "fold": {"lookups": sum(prof.lookups[i] for i in ks) / reps,
                     "terms": sum(prof.splits[i] for i in ks) / reps}}
     return out
