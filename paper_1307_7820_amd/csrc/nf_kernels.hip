@@ -769,6 +769,11 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                 }
                 fetch_edges(rr > 0 ? blk : blk - 1, rr > 0 ? rr - 1 : 7, ern, ecn);
             }
+            // pairing of (i-1, j) with partner X(i, j-1), for the next row's
+            // Q: its bit, or -inf where there is no partner (formed here,
+            // off the chain)
+            int pb = (i >= 1 && i < T && c > 0) ? (int)((pmask >> ((i - 1) >> 3)) & 1u) : kNeg;
+            __asm__ volatile("" : "+v"(pb));  // kept here, not sunk into the write below
             __builtin_amdgcn_sched_barrier(0);
             // the end-tile terms of this row's share into the rows of block
             // blk-1 (Eq. 3; the term's value in the low 16 bits, see rterm)
@@ -791,12 +796,19 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                     }
                 }
             };
-            int q0 = qa.x;
-            if (i < T - 1 && g > 0) q0 = max(q0, (int)((gmask >> i) & 1u) + xl);
-            // closure over j' in [8g, 8g+8), then across the 8 lane groups
-            int p = max(max(q0 + ureg[0], qa.y + ureg[1]), max(qa.z + ureg[2], qa.w + ureg[3]));
-            p = max(p, max(max(qb.x + ureg[4], qb.y + ureg[5]), max(qb.z + ureg[6], qb.w + ureg[7])));
-            const int xi = max_over_groups(p);  // X(i, j)
+            // the pairing term of cell (i, 8g) (partner X(i+1, 8g-1)) is a
+            // candidate for Q(i, 8g): it joins the closure at split point 8g
+            // as one more term, formed before Q arrives
+            // (X(i, j) >= 0, so 0 stands for no candidate)
+            int pt = 0;
+            if (i < T - 1 && g > 0) pt = (int)((gmask >> i) & 1u) + xl + ureg[0];
+            // closure over j' in [8g, 8g+8) as a tree of 3-input maxima (the
+            // chain after the Q read: an add and two levels), then across the
+            // 8 lane groups
+            const int m0 = max(max(qa.x + ureg[0], qa.y + ureg[1]), qa.z + ureg[2]);
+            const int m1 = max(max(qa.w + ureg[3], qb.x + ureg[4]), qb.y + ureg[5]);
+            const int m2 = max(max(qb.z + ureg[6], qb.w + ureg[7]), pt);
+            const int xi = max_over_groups(max(max(m0, m1), m2));  // X(i, j)
             __builtin_amdgcn_sched_barrier(0);
             // pushes of row i: into row 8*blk+g (one split; -inf unless the row
             // is above i), or for other q into every row above
@@ -839,11 +851,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                 // they read does not matter (lanes 0, 16, 32, 48 read 0)
                 const int left = __builtin_amdgcn_mov_dpp(xi, 0x111, 0xF, 0xF, true);
                 const int go = (i - 1) & 7, bo = (i - 1) >> 3;
-                if (g == go) {
-                    int qv = acc[bo];
-                    if (i < T && c > 0) qv = max(qv, (int)((pmask >> bo) & 1u) + left);
-                    Qs[(i - 1) & 1][j] = qv;
-                }
+                if (g == go) Qs[(i - 1) & 1][j] = max(acc[bo], left + pb);
             }
             if (g == 0) Xs[i * 64 + j] = (Cell)xi;
             if (rr > 0) edge_terms();
