@@ -297,8 +297,8 @@ int nf_autotune_target(int n, int q);
  * NF_E_INVAL for n or q out of range. */
 int nf_autotune_wide(int n, int q);
 /* Time the fill at length n (reps folds each, after one warm-up fold): first
- * q in qmin..qmax at the default target, then the targets 1024, 256, 512 and
- * 2048 at the fastest q, then (q = 8) the other fused-step shape.  Records
+ * q in qmin..qmax at the default target, then the targets 1024, 256, 512,
+ * 2048 and 2560 at the fastest q, then (q = 8) the other fused-step shape.  Records
  * all three in the in-memory cache (and in the cache file if set).  Returns
  * the chosen q. */
 int nf_autotune(int n, int qmin, int qmax, int reps);

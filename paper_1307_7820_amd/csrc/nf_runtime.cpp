@@ -883,7 +883,7 @@ int autotune_run(int n, int qmin, int qmax, int reps)
     }
     best_ms = 1e30f;
     int best_w = default_wide(best_q);
-    for (int t : {kDefaultTarget, 256, 512, 2048}) {
+    for (int t : {kDefaultTarget, 256, 512, 2048, 2560}) {
         if (rc) break;
         if ((rc = time_plan(best_q, t, best_w, &ms))) break;
         if (ms < best_ms) {

@@ -100,7 +100,7 @@ def test_n6000_full_table_as_benched(nf):
     s = gen.workload_n6000()
     q = nf.nf_autotune(len(s), 4, 8, 5)
     assert nf.nf_autotune_q(len(s)) == q
-    assert nf.nf_autotune_target(len(s)) in (1024, 256, 512, 2048)
+    assert nf.nf_autotune_target(len(s)) in (1024, 256, 512, 2048, 2560)
     score, T = nf.nf_fold(s, q=0, table=True)
     assert np.array_equal(T, oracle.fold_table(s))
 
@@ -174,7 +174,7 @@ def test_autotune_picks_and_caches(nf):
     q = nf.nf_autotune(1500, 4, 8, 1)
     assert 4 <= q <= 8
     assert nf.nf_autotune_q(1500) == q
-    assert nf.nf_autotune_target(1500) in (1024, 256, 512, 2048)
+    assert nf.nf_autotune_target(1500) in (1024, 256, 512, 2048, 2560)
     assert nf.nf_autotune_target(1500, 5 if q == 4 else 4) == 1024  # tuned for q only
     # a fold with q = 0 uses the tuned value and still matches the oracle
     s = gen.iid_sequence(1500, [111, 0])
