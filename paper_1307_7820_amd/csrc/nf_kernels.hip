@@ -92,11 +92,20 @@ __device__ __forceinline__ uint32_t max3_u16(uint32_t a, uint32_t b, uint32_t c)
     return d;
 }
 
-// Copy the q-dependent R table (RSZ bytes) into LDS.
+// Copy the q-dependent R table (RSZ bytes) into LDS.  From 1 KB on by DMA
+// (global -> LDS, no registers and no LDS store; a wave moves 1 KB and RSZ is
+// a multiple of it, so no lane reads past R or writes past Rl), waited for
+// here; below that through registers.  The caller's barrier follows.
 template <int RSZ>
 __device__ __forceinline__ void load_R(uint8_t* Rl, const uint8_t* __restrict__ Rg, int nthr)
 {
-    if constexpr (RSZ >= 16) {
+    if constexpr (RSZ >= 1024) {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+        for (int base = wave * 1024; base < RSZ; base += nthr * 16)  // wave-uniform
+            __builtin_amdgcn_global_load_lds((const NF_GLOBAL void*)(Rg + base + lane * 16),
+                                             (__attribute__((address_space(3))) void*)(Rl + base), 16, 0, 0);
+        __builtin_amdgcn_s_waitcnt(0);
+    } else if constexpr (RSZ >= 16) {
         for (int x = threadIdx.x * 16; x < RSZ; x += nthr * 16)
             *reinterpret_cast<uint4*>(Rl + x) = *reinterpret_cast<const uint4*>(Rg + x);
     } else {
