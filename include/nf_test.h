@@ -54,7 +54,7 @@ int nf_test_set_perturb(unsigned seed);
  * row word of row a and group k of tile (A, B) holds the base F(a, BT+kq) in
  * bits 15..0 and, above it, h << (q-1) with bit p-1 of h the difference
  * F(a, BT+kq+p) - F(a, BT+kq+p-1) (Lemma 1: 0 or 1), p = 1..q-1; the column
- * word of column b holds F(AT+kq, b) in bits 31..16 and in bits 15..0 c, bit
+ * word of column b holds F(AT+kq, b) in bits 15..0 and in bits 31..16 c, bit
  * p-1 of c = F(AT+kq+p-1, b) - F(AT+kq+p, b).  Here F(a, b) = D(a+1, b) over
  * posts 0..NT*T-1, T = (64/q)*q, with the sequence padded by 'A' to
  * NT*T - 1 bases; rows and columns >= T are zero words.  The blocks of

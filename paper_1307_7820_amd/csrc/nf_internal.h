@@ -23,16 +23,16 @@
 //       bits 31..16 = h << (q-1), bit p-1 of h = F(a, BT+kq+p) - F(a, BT+kq+p-1)
 //       bits 15..0  = F(a, BT+kq)                (Eq. 3 "D(i,l)")
 //   column word (group k of the tile's rows, column j):
-//       bits 31..16 = F(AT+kq, b)                (Eq. 3 "D(l+1,j)")
-//       bits 15..0  = c, bit p-1 of c = F(AT+kq+p-1, b) - F(AT+kq+p, b)
+//       bits 31..16 = c, bit p-1 of c = F(AT+kq+p-1, b) - F(AT+kq+p, b)
+//       bits 15..0  = F(AT+kq, b)                (Eq. 3 "D(l+1,j)")
 // Scores are below 2^15 and h << (q-1) | c below 2^16 for q <= 9.  Per tile
 // the row block and the column block are each [k][64] (rows/columns >= T
 // unused), so one group of one tile is one 256-byte line.  The Four-Russians
 // step of Eq. 3 for cell (a, b) and group K is then
-//     (rw & 0xffff) + (cw >> 16) + R[(rw >> 16) + (cw & 0xffff)]
+//     (rw & 0xffff) + (cw & 0xffff) + R[(rw >> 16) + (cw >> 16)]
 // with the row word rw read wave-uniformly.  Every such term is one split of
-// Eq. 1, so it is at most F(a, b) < 2^15: the low half of rw + (cw >> 16) + R
-// holds it without a carry, whatever the high half of rw holds.
+// Eq. 1, so it is at most F(a, b) < 2^15: the low half of rw + cw + R holds
+// it without a carry, whatever the high halves hold.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -51,12 +51,12 @@ __device__ __forceinline__ const NF_CONST T* as_const(const T* p)
 }
 
 // R index of a row word held in a scalar register and a column word: bits
-// 31..16 of the row word plus bits 15..0 of the column word, one VALU
-// instruction (SDWA selects both halves; an ALU operation, not a load).
+// 31..16 of each, one VALU instruction (SDWA selects both high halves; an
+// ALU operation, not a load).
 __device__ __forceinline__ uint32_t r_index_s(uint32_t rw, uint32_t cw)
 {
     uint32_t idx;
-    __asm__("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:WORD_0"
+    __asm__("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:WORD_1"
             : "=v"(idx)
             : "s"(rw), "v"(cw));
     return idx;
@@ -66,7 +66,7 @@ __device__ __forceinline__ uint32_t r_index_s(uint32_t rw, uint32_t cw)
 __device__ __forceinline__ uint32_t r_index_v(uint32_t rw, uint32_t cw)
 {
     uint32_t idx;
-    __asm__("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:WORD_0"
+    __asm__("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:WORD_1"
             : "=v"(idx)
             : "v"(rw), "v"(cw));
     return idx;
@@ -121,11 +121,12 @@ __device__ __forceinline__ void load_R(uint8_t* Rl, const uint8_t* __restrict__ 
 // With NS > 1 the caller's share is every NS-th group of the flattened
 // (C, k) sequence, starting at group h.
 //
-// A lookup is three VALU instructions' worth: the R index (one SDWA add of
-// the scalar row word's high half and the column word's low half), one
-// 3-input add of the whole row word, the column base and R (its low half is
-// the split's value, see the packed words), and half of a 16-bit 3-input max
-// over two groups.  acc holds its maxima in the low 16 bits.
+// A lookup is two and a half VALU instructions: the R index (one SDWA add of
+// the high halves of the scalar row word and the column word), one 3-input
+// add of the whole row word, the whole column word and R (the low halves
+// hold the two bases, so the low half of the sum is the split's value, see
+// the packed words), and half of a 16-bit 3-input max over two groups.  acc
+// holds its maxima in the low 16 bits.
 template <int Q, int RPW, int NS>
 __device__ __forceinline__ void between_accumulate(int (&acc)[RPW], const uint8_t* Rl,
                                                    const uint32_t* __restrict__ RS,
@@ -171,13 +172,11 @@ __device__ __forceinline__ void between_accumulate(int (&acc)[RPW], const uint8_
                     load_cw(C + 1, 0);
 #pragma unroll
                 for (int v = 0; v < KB; v += 2) {
-                    const uint32_t chi0 = cw[v] >> 16;
-                    const uint32_t chi1 = v + 1 < KB ? cw[v + 1] >> 16 : 0u;
 #pragma unroll
                     for (int r = 0; r < RPW; ++r) {
-                        const uint32_t t0 = rw[v][r] + chi0 + Rl[r_index_s(rw[v][r], cw[v])];
+                        const uint32_t t0 = rw[v][r] + cw[v] + Rl[r_index_s(rw[v][r], cw[v])];
                         const uint32_t t1 =
-                            v + 1 < KB ? rw[v + 1][r] + chi1 + Rl[r_index_s(rw[v + 1][r], cw[v + 1])] : 0u;
+                            v + 1 < KB ? rw[v + 1][r] + cw[v + 1] + Rl[r_index_s(rw[v + 1][r], cw[v + 1])] : 0u;
                         acc[r] = (int)max3_u16((uint32_t)acc[r], t0, t1);
                     }
                 }
@@ -191,11 +190,10 @@ __device__ __forceinline__ void between_accumulate(int (&acc)[RPW], const uint8_
 #pragma unroll 2
             for (int k = k0; k < G; k += NS) {
                 const uint32_t cw = cs[k * 64];
-                const uint32_t chi = cw >> 16;
 #pragma unroll
                 for (int r = 0; r < RPW; ++r) {
                     const uint32_t rw = rs[k * 64 + r];
-                    const uint32_t t = rw + chi + Rl[r_index_s(rw, cw)];
+                    const uint32_t t = rw + cw + Rl[r_index_s(rw, cw)];
                     acc[r] = (int)max3_u16((uint32_t)acc[r], t, 0u);
                 }
             }
@@ -400,16 +398,16 @@ constexpr int kNeg = -(1 << 20);  // stands for minus infinity; sums stay far fr
 template <int Q>
 __device__ __forceinline__ int rlookup(const uint8_t* Rl, uint32_t rw, uint32_t cw)
 {
-    return (int)((rw & 0xffffu) + (cw >> 16)) + (int)Rl[(rw >> 16) + (cw & 0xffffu)];
+    return (int)((rw & 0xffffu) + (cw & 0xffffu)) + (int)Rl[(rw >> 16) + (cw >> 16)];
 }
 
 // The Eq. 3 term of a row word and a column word in the low 16 bits of the
-// result (the whole row word is added: the term is one split of a cell, so it
+// result (the whole words are added: the term is one split of a cell, so it
 // stays below 2^15 and nothing carries out of the low half; the high half is
 // not meaningful).  Both words in vector registers.
 __device__ __forceinline__ uint32_t rterm(const uint8_t* Rl, uint32_t rw, uint32_t cw)
 {
-    return rw + (cw >> 16) + (uint32_t)Rl[r_index_v(rw, cw)];
+    return rw + cw + (uint32_t)Rl[r_index_v(rw, cw)];
 }
 
 // max of v over the 8 lanes l ^ {8, 16, 32} (lanes 8g + c, g = 0..7)
@@ -795,9 +793,9 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                             const int m1 = m + 1 < kEPer ? m + 1 : m;
                             const int x0 = rr + 8 * m, x1 = rr + 8 * (m + 1);
                             if (x0 >= NE) continue;  // x0 = rr < 8 < NE when m = 0
-                            const uint32_t t0 = erw[m] + ((kLean ? erc[m] : col_word(x0)) >> 16) + rg[m];
+                            const uint32_t t0 = erw[m] + (kLean ? erc[m] : col_word(x0)) + rg[m];
                             const uint32_t t1 = (m + 1 < kEPer && x1 < NE)
-                                                    ? erw[m1] + ((kLean ? erc[m1] : col_word(x1)) >> 16) + rg[m1]
+                                                    ? erw[m1] + (kLean ? erc[m1] : col_word(x1)) + rg[m1]
                                                     : t0;
                             ev = max3_u16(m == 0 ? t0 : ev, t0, t1);
                         }
@@ -844,7 +842,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                         uint32_t cbits = 0;
 #pragma unroll
                         for (int p2 = 1; p2 <= M; ++p2) cbits |= (uint32_t)(xs[p2 - 1] > xs[p2]) << (p2 - 1);
-                        const uint32_t cw = ((uint32_t)xs[0] << 16) | cbits;
+                        const uint32_t cw = (cbits << 16) | (uint32_t)xs[0];
                         const uint4 wa = *reinterpret_cast<const uint4*>(&LW[k * 64 + 8 * g]);
                         const uint4 wb = *reinterpret_cast<const uint4*>(&LW[k * 64 + 8 * g + 4]);
                         const uint32_t ws[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
@@ -912,7 +910,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
 #pragma unroll
             for (int p = 1; p <= M; ++p)
                 cbits |= (uint32_t)(Xs[(top + p - 1) * 64 + jj] > Xs[(top + p) * 64 + jj]) << (p - 1);
-            CSw[k * 64 + jj] = ((uint32_t)(uint16_t)Xs[top * 64 + jj] << 16) | cbits;
+            CSw[k * 64 + jj] = (cbits << 16) | (uint32_t)(uint16_t)Xs[top * 64 + jj];
         } else {
             CSw[k * 64 + jj] = 0;  // padding column, as for padding rows
         }

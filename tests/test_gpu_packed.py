@@ -5,7 +5,7 @@ Lemma 1's 0/1 differences), read back through nf_test_packed_state.
 For tile (A, B), row a and group k of its columns, the row word holds the
 base F(a, BT+kq) in its low half and h << (q-1) above it, bit p-1 of h being
 F(a, BT+kq+p) - F(a, BT+kq+p-1); for column b and group k of its rows, the
-column word holds F(AT+kq, b) in its high half and c in its low half, bit
+column word holds F(AT+kq, b) in its low half and c in its high half, bit
 p-1 of c being F(AT+kq+p-1, b) - F(AT+kq+p, b).  F(a, b) = D(a+1, b), posts
 past n taken from the sequence padded with 'A'.  Rows and columns at or past
 T = (64/q)q are zero words.  Every word of every off-diagonal tile is
@@ -53,7 +53,7 @@ def _expected_blocks(F, q, A, B):
     assert dc.min(initial=0) >= 0 and dc.max(initial=0) <= 1  # Lemma 1 down columns
     c = np.einsum("gpt,p->gt", dc, w) if q > 1 else np.zeros((G, T), dtype=np.int64)
     col = np.zeros((G, 64), dtype=np.int64)
-    col[:, :T] = (c3[:, 0, :] << 16) | c
+    col[:, :T] = (c << 16) | c3[:, 0, :]
     return row.astype(np.uint32), col.astype(np.uint32)
 
 
