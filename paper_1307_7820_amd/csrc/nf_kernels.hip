@@ -439,7 +439,10 @@ struct TileLds {
     uint32_t LW[kBlockFR ? G * 64 : 4];  // LW[k*64 + 8g + b]: row word of row 8b+g, group k, tile (A, A)
     uint32_t EB[kStageEdges ? 2 * G * 64 : 1];  // EB[(e*G + k)*64 + row] = row word, end tile e
     uint32_t EC[kStageEdges ? 2 * G * 64 : 1];  // EC[(e*G + k)*64 + col] = column word, end tile e
-    int32_t Qs[2][64];    // Q of the row being closed (double-buffered)
+    // Q of the row being closed (double-buffered); 16-bit in the lean form,
+    // where the closure runs on packed pairs
+    using QCell = typename std::conditional<kLean, int16_t, int32_t>::type;
+    alignas(16) QCell Qs[2][64];
     int32_t hrow[64];
     alignas(16) int32_t hcT[64];  // hcT[8g + b] = halo partner of column 0 in row 8b + g
     alignas(16) uint8_t caT[64];  // caT[8g + b] = S_{a+1} of row 8b + g
@@ -475,7 +478,8 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     uint32_t* LW = s.LW;
     uint32_t* EB = s.EB;
     uint32_t* EC = s.EC;
-    int32_t (*Qs)[64] = s.Qs;
+    using QCell = typename Lds::QCell;
+    QCell (*Qs)[64] = s.Qs;
     int32_t* hrow = s.hrow;
     int32_t* hcT = s.hcT;
     uint8_t* caT = s.caT;
@@ -718,7 +722,20 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
 
     // ---- rows bottom-up.  Rows >= T (only when T < 64) are inert: their
     // pushes are -inf in Lp and their pairing into row T-1 is skipped.
-    if (g == 7) Qs[1][j] = acc[7];  // row 63: Q complete (no row below)
+    if (g == 7) Qs[1][j] = (QCell)acc[7];  // row 63: Q complete (no row below)
+    // Lean form: U as pairs of 16-bit values for the packed closure, with
+    // -2^15 for minus infinity.  Every real sum Q(i, j') + U(j', j) is at
+    // most X(i, j) < 2^15 and Q >= 0, so no sum leaves the 16-bit range.
+    // u0p is U(8g, j) for the pairing term, -2^15 also where g = 0 (that
+    // lane's term then stays <= 0, which no cell is below).
+    uint32_t up[4] = {0u, 0u, 0u, 0u};
+    int u0p = 0;
+    if constexpr (kLean) {
+        auto h16 = [](int v) { return (uint32_t)(v < 0 ? 0x8000 : v); };
+#pragma unroll
+        for (int t = 0; t < 4; ++t) up[t] = h16(ureg[2 * t]) | (h16(ureg[2 * t + 1]) << 16);
+        u0p = (g > 0 && ureg[0] >= 0) ? ureg[0] : -32768;
+    }
     // end-tile row and column words of the share of row (bb, r): groups
     // x = r + 8m of block bb-1, loaded one row step ahead of their use
     // (erw/erc: this row's, ern/ecn: the next row's, fetched while this row
@@ -748,7 +765,8 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             // the pushes, and the end-tile words of this row's share of
             // block blk-1
             const int4 qa = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g]);
-            const int4 qb = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g + 4]);
+            int4 qb = make_int4(0, 0, 0, 0);  // (the lean form's 8 values are all in qa)
+            if constexpr (!kLean) qb = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g + 4]);
             int xl = kNeg;
             if (i < T - 1) xl = Xs[(i + 1) * 64 + 8 * g - 1];  // X(i+1, 8g-1); unused for g = 0
             int lp[8];
@@ -808,14 +826,33 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             // as one more term, formed before Q arrives
             // (X(i, j) >= 0, so 0 stands for no candidate)
             int pt = 0;
-            if (i < T - 1 && g > 0) pt = (int)((gmask >> i) & 1u) + xl + ureg[0];
-            // closure over j' in [8g, 8g+8) as a tree of 3-input maxima (the
-            // chain after the Q read: an add and two levels), then across the
-            // 8 lane groups
-            const int m0 = max(max(qa.x + ureg[0], qa.y + ureg[1]), qa.z + ureg[2]);
-            const int m1 = max(max(qa.w + ureg[3], qb.x + ureg[4]), qb.y + ureg[5]);
-            const int m2 = max(max(qb.z + ureg[6], qb.w + ureg[7]), pt);
-            const int xi = max_over_groups(max(max(m0, m1), m2));  // X(i, j)
+            if constexpr (kLean) {
+                if (i < T - 1) pt = (int)((gmask >> i) & 1u) + xl + u0p;
+            } else {
+                if (i < T - 1 && g > 0) pt = (int)((gmask >> i) & 1u) + xl + ureg[0];
+            }
+            // closure over j' in [8g, 8g+8), then across the 8 lane groups.
+            // Default form: a tree of 3-input maxima (the chain after the Q
+            // read: an add and two levels).  Lean form, where the finish is
+            // bound by instruction issue rather than by its chain: packed
+            // 16-bit adds and maxima over the pairs, then the two halves.
+            int xc;
+            if constexpr (kLean) {
+                typedef short s16x2 __attribute__((ext_vector_type(2)));
+                const s16x2 a0 = __builtin_bit_cast(s16x2, qa.x) + __builtin_bit_cast(s16x2, up[0]);
+                const s16x2 a1 = __builtin_bit_cast(s16x2, qa.y) + __builtin_bit_cast(s16x2, up[1]);
+                const s16x2 a2 = __builtin_bit_cast(s16x2, qa.z) + __builtin_bit_cast(s16x2, up[2]);
+                const s16x2 a3 = __builtin_bit_cast(s16x2, qa.w) + __builtin_bit_cast(s16x2, up[3]);
+                const s16x2 mm = __builtin_elementwise_max(__builtin_elementwise_max(a0, a1),
+                                                           __builtin_elementwise_max(a2, a3));
+                xc = max(max((int)mm.x, (int)mm.y), pt);
+            } else {
+                const int m0 = max(max(qa.x + ureg[0], qa.y + ureg[1]), qa.z + ureg[2]);
+                const int m1 = max(max(qa.w + ureg[3], qb.x + ureg[4]), qb.y + ureg[5]);
+                const int m2 = max(max(qb.z + ureg[6], qb.w + ureg[7]), pt);
+                xc = max(max(m0, m1), m2);
+            }
+            const int xi = max_over_groups(xc);  // X(i, j)
             __builtin_amdgcn_sched_barrier(0);
             // pushes of row i: into row 8*blk+g (one split; -inf unless the row
             // is above i), or for other q into every row above
@@ -826,8 +863,11 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                 for (int b = 0; b <= blk; ++b) acc[b] = max(acc[b], lp[b] + xi);
             }
             // the last row of a block: the next row (in block blk-1) takes
-            // its Q from acc[blk-1] now, so its end-tile terms go in first
-            if (rr == 0) edge_terms();
+            // its Q from acc[blk-1] now, so its end-tile terms go in first.
+            // The lean form sums them here at every row, in the same block
+            // of code as their gathers (after the writes below, the loaded
+            // bytes would need masking again)
+            if (kLean || rr == 0) edge_terms();
             if constexpr (kBlockFR) {
                 if (rr == 0 && blk >= 1) {
                     // block blk finished: its q-groups into every row above it
@@ -858,10 +898,10 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                 // they read does not matter (lanes 0, 16, 32, 48 read 0)
                 const int left = __builtin_amdgcn_mov_dpp(xi, 0x111, 0xF, 0xF, true);
                 const int go = (i - 1) & 7, bo = (i - 1) >> 3;
-                if (g == go) Qs[(i - 1) & 1][j] = max(acc[bo], left + pb);
+                if (g == go) Qs[(i - 1) & 1][j] = (QCell)max(acc[bo], left + pb);
             }
             if (g == 0) Xs[i * 64 + j] = (Cell)xi;
-            if (rr > 0) edge_terms();
+            if (!kLean && rr > 0) edge_terms();
             if constexpr (kStageEdges) {
 #pragma unroll
                 for (int m = 0; m < kEPer; ++m) {
