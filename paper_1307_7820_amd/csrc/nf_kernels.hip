@@ -534,18 +534,22 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             rbyte = ((const NF_GLOBAL uint8_t*)Rg)[min(tid, RSZ - 1)];
         }
     }
-    int lv[8];
+    // Addresses below are a wave-uniform base (scalar arithmetic) plus a
+    // 32-bit lane offset, so the loads need almost no vector instructions.
+    int lv[8];  // L(ip, lane) for the row ip = wave + 8u of tile (A, A), read coalesced
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-        const int e = tid + u * kTileThreads;
-        const int ip = e >> 6, i = e & 63;  // row ip of L, read coalesced
-        lv[u] = (ip < i && i < T) ? (int)F[(aT + ip) * ld + aT + i] : kNeg;
+        const int ip = wave + 8 * u;
+        const NF_GLOBAL int16_t* Lrow = F + (long long)(aT + ip) * ld + aT;
+        lv[u] = (ip < lane && lane < T) ? (int)Lrow[(unsigned)lane] : kNeg;
     }
     int ureg[8];  // U(8g + t, j); -inf where the split point is not left of column j
+    const unsigned uoff = (unsigned)(8 * g) * (unsigned)ld + (unsigned)j;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int jp = 8 * g + t;
-        ureg[t] = (jp <= j && j < T) ? (int)F[(bT + jp) * ld + bT + j] : kNeg;
+        const NF_GLOBAL int16_t* Urow = F + (long long)(bT + t) * ld + bT;
+        ureg[t] = (jp <= j && j < T) ? (int)Urow[uoff] : kNeg;
     }
     uint8_t cda = 0, cdb = 0;
     if (tid < 64) {
@@ -556,10 +560,11 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     // part 2: the between maxima, the end tiles and the halo
     wait_main();
     int acc[8];  // acc[b]: row 8b + g, column j
-    NF_GLOBAL int32_t* accp = (NF_GLOBAL int32_t*)(it.acc + g * 64 + j);
+    NF_GLOBAL int32_t* accb = (NF_GLOBAL int32_t*)it.acc;
+    const unsigned aoff = (unsigned)(g * 64 + j);
     if (it.nslot > 0) {
 #pragma unroll
-        for (int b = 0; b < 8; ++b) acc[b] = accp[b * 512];
+        for (int b = 0; b < 8; ++b) acc[b] = (accb + b * 512)[aoff];
     } else {
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[b] = 0;
@@ -574,14 +579,13 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     if constexpr (kStageEdges) {
 #pragma unroll
         for (int u = 0; u < kIter; ++u) {
-            const int x = tid + u * kTileThreads;
-            const int eg = x >> 6, r = x & 63;
+            const int eg = wave + u * (kTileThreads / 64);  // (tid + u * kTileThreads) >> 6, wave-uniform
             const int e = eg / G, k = eg - e * G;
             const int C = e == 0 ? A + 1 : B - 1;
             rb[u] = cw[u] = 0;
-            if (x < 2 * G * 64) {
-                rb[u] = RSr[tile_index(f.NT, A, C - A) * RW + k * 64 + r];
-                cw[u] = CSr[tile_index(f.NT, C, B - C) * SW + k * 64 + r];
+            if (eg < 2 * G) {
+                rb[u] = (RSr + tile_index(f.NT, A, C - A) * RW + k * 64)[(unsigned)lane];
+                cw[u] = (CSr + tile_index(f.NT, C, B - C) * SW + k * 64)[(unsigned)lane];
             }
         }
     }
@@ -622,7 +626,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     *reinterpret_cast<int4*>(&Lp[lane * LS + 8 * wave + 4]) = make_int4(lv[4], lv[5], lv[6], lv[7]);
     if (it.nslot > 0) {  // hand the accumulator back zeroed for its next use
 #pragma unroll
-        for (int b = 0; b < 8; ++b) accp[b * 512] = 0;
+        for (int b = 0; b < 8; ++b) (accb + b * 512)[aoff] = 0;
     }
     if constexpr (kLoadR && RSZ >= 1024) __builtin_amdgcn_s_waitcnt(0);  // the R transfer (vector memory counter) is done
     __syncthreads();
@@ -928,7 +932,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             const int i = wv * 8 + r;
             const int v = xv[r];
             if (i < T) {
-                if (ln < T) Fw[(aT + i) * ld + bT + ln] = (int16_t)v;
+                if (ln < T) (Fw + (long long)(aT + i) * ld + bT)[(unsigned)ln] = (int16_t)v;
                 const unsigned long long diff = __ballot(ln > 0 && ln < T && v > xlft[r]);
                 if (ln < T && (ln % Q) == 0) {
                     uint32_t h = 0;
