@@ -918,6 +918,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     }
 
     // ---- emit: dense cells, row words (ballot), column words
+    int xcol[8];  // X(8 * wave + r, lane)
     {
         const int wv = wave, ln = lane;  // row-major view: wave -> 8 rows, lane -> column
         int xv[8], xlft[8];  // every LDS read first: X(i, ln) and X(i, ln-1)
@@ -927,6 +928,8 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             xv[r] = Xs[i * 64 + ln];
             xlft[r] = Xs[i * 64 + max(ln - 1, 0)];
         }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) xcol[r] = xv[r];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int i = wv * 8 + r;
@@ -946,6 +949,14 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             }
         }
     }
+    if constexpr (Q == 8) {
+        // q = 8: group k = wave holds rows 8k..8k+7, this lane's xv[], so
+        // the column word of (group wave, column lane) needs no LDS reads
+        uint32_t cbits = 0;
+#pragma unroll
+        for (int p = 1; p <= M; ++p) cbits |= (uint32_t)(xcol[p - 1] > xcol[p]) << (p - 1);
+        CSw[wave * 64 + lane] = (cbits << 16) | (uint32_t)(uint16_t)xcol[0];
+    } else
     for (int e = tid; e < G * 64; e += kTileThreads) {
         const int k = e >> 6, jj = e & 63;
         if (jj < T) {
