@@ -424,6 +424,19 @@ __device__ __forceinline__ int max_over_groups(int v)
 // kLean: the finish's lean form for the wide fused step (fewer registers and
 // less LDS): finished cells kept as 16-bit values and the end tiles' column
 // words read from LDS a row step ahead instead of held in registers.
+// The 7 difference bits of 8 values that fall by 0 or 1 from each to the
+// next (a column of the table going down, Lemma 1): bit p-1 is
+// x[p-1] - x[p].  As integers that is the sum over p of
+// (x[p-1] - x[p]) 2^(p-1) = x0 + x1 + 2 x2 + 4 x3 + 8 x4 + 16 x5 + 32 x6 - 64 x7,
+// formed here as a tree of shift-adds three deep (7 instructions instead of
+// a compare, a select and an or per bit).
+__device__ __forceinline__ uint32_t drop_bits8(const int (&x)[8])
+{
+    const int t0123 = (x[0] + x[1]) + ((x[2] + (x[3] << 1)) << 1);
+    const int t4567 = (x[4] + (x[5] << 1)) + ((x[6] - (x[7] << 1)) << 2);
+    return (uint32_t)(t0123 + (t4567 << 3));
+}
+
 template <int Q, bool kLean>
 struct TileLds {
     static constexpr int G = groups_per_tile(Q);
@@ -641,9 +654,17 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             int base = 0;
             if (top > r && top < T) {
                 base = Lp[top * LS + pos];
+                if constexpr (Q == 8) {
+                    // along a row the values rise by 0 or 1 (Lemma 1)
+                    int v[8];
 #pragma unroll
-                for (int p = 1; p <= M; ++p)
-                    h |= (uint32_t)(Lp[(top + p) * LS + pos] > Lp[(top + p - 1) * LS + pos]) << (p - 1);
+                    for (int p = 0; p < 8; ++p) v[p] = Lp[(top + p) * LS + pos];
+                    h = 0u - drop_bits8(v);
+                } else {
+#pragma unroll
+                    for (int p = 1; p <= M; ++p)
+                        h |= (uint32_t)(Lp[(top + p) * LS + pos] > Lp[(top + p - 1) * LS + pos]) << (p - 1);
+                }
             }
             LW[x] = ((h << M) << 16) | (uint32_t)base;
         }
@@ -884,8 +905,12 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
 #pragma unroll
                         for (int p2 = 0; p2 < Q; ++p2) xs[p2] = (top + p2 == i) ? xi : Xs[(top + p2) * 64 + j];
                         uint32_t cbits = 0;
+                        if constexpr (Q == 8) {
+                            cbits = drop_bits8(xs);
+                        } else {
 #pragma unroll
-                        for (int p2 = 1; p2 <= M; ++p2) cbits |= (uint32_t)(xs[p2 - 1] > xs[p2]) << (p2 - 1);
+                            for (int p2 = 1; p2 <= M; ++p2) cbits |= (uint32_t)(xs[p2 - 1] > xs[p2]) << (p2 - 1);
+                        }
                         const uint32_t cw = (cbits << 16) | (uint32_t)xs[0];
                         const uint4 wa = *reinterpret_cast<const uint4*>(&LW[k * 64 + 8 * g]);
                         const uint4 wb = *reinterpret_cast<const uint4*>(&LW[k * 64 + 8 * g + 4]);
@@ -952,10 +977,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     if constexpr (Q == 8) {
         // q = 8: group k = wave holds rows 8k..8k+7, this lane's xv[], so
         // the column word of (group wave, column lane) needs no LDS reads
-        uint32_t cbits = 0;
-#pragma unroll
-        for (int p = 1; p <= M; ++p) cbits |= (uint32_t)(xcol[p - 1] > xcol[p]) << (p - 1);
-        CSw[wave * 64 + lane] = (cbits << 16) | (uint32_t)(uint16_t)xcol[0];
+        CSw[wave * 64 + lane] = (drop_bits8(xcol) << 16) | (uint32_t)(uint16_t)xcol[0];
     } else
     for (int e = tid; e < G * 64; e += kTileThreads) {
         const int k = e >> 6, jj = e & 63;
