@@ -752,15 +752,19 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     // -2^15 for minus infinity.  Every real sum Q(i, j') + U(j', j) is at
     // most X(i, j) < 2^15 and Q >= 0, so no sum leaves the 16-bit range.
     // u0p is U(8g, j) for the pairing term, -2^15 also where g = 0 (that
-    // lane's term then stays <= 0, which no cell is below).
+    // lane's term then stays <= 0, which no cell is below; the default form
+    // uses -inf there).
     uint32_t up[4] = {0u, 0u, 0u, 0u};
-    int u0p = 0;
+    int u0p;
     if constexpr (kLean) {
         auto h16 = [](int v) { return (uint32_t)(v < 0 ? 0x8000 : v); };
 #pragma unroll
         for (int t = 0; t < 4; ++t) up[t] = h16(ureg[2 * t]) | (h16(ureg[2 * t + 1]) << 16);
         u0p = (g > 0 && ureg[0] >= 0) ? ureg[0] : -32768;
+    } else {
+        u0p = g > 0 ? ureg[0] : kNeg;  // (the pairing term then needs no select per row)
     }
+    const int xlc = g > 0 ? 8 * g - 1 : 0;
     // end-tile row and column words of the share of row (bb, r): groups
     // x = r + 8m of block bb-1, loaded one row step ahead of their use
     // (erw/erc: this row's, ern/ecn: the next row's, fetched while this row
@@ -793,7 +797,10 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             int4 qb = make_int4(0, 0, 0, 0);  // (the lean form's 8 values are all in qa)
             if constexpr (!kLean) qb = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g + 4]);
             int xl = kNeg;
-            if (i < T - 1) xl = Xs[(i + 1) * 64 + 8 * g - 1];  // X(i+1, 8g-1); unused for g = 0
+            // X(i+1, 8g-1); lanes of slice 0 read the finished X(i+1, 0)
+            // instead, so that their pairing term stays finite and, with
+            // u0p, below every cell
+            if (i < T - 1) xl = Xs[(i + 1) * 64 + xlc];
             int lp[8];
             if constexpr (kBlockFR) {
                 lp[blk] = Lp[i * LS + 8 * g + blk];
@@ -851,11 +858,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             // as one more term, formed before Q arrives
             // (X(i, j) >= 0, so 0 stands for no candidate)
             int pt = 0;
-            if constexpr (kLean) {
-                if (i < T - 1) pt = (int)((gmask >> i) & 1u) + xl + u0p;
-            } else {
-                if (i < T - 1 && g > 0) pt = (int)((gmask >> i) & 1u) + xl + ureg[0];
-            }
+            if (i < T - 1) pt = (int)((gmask >> i) & 1u) + xl + u0p;
             // closure over j' in [8g, 8g+8), then across the 8 lane groups.
             // Default form: a tree of 3-input maxima (the chain after the Q
             // read: an add and two levels).  Lean form, where the finish is
