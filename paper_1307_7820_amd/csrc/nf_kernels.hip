@@ -452,9 +452,12 @@ struct TileLds {
     uint32_t LW[kBlockFR ? G * 64 : 4];  // LW[k*64 + 8g + b]: row word of row 8b+g, group k, tile (A, A)
     uint32_t EB[kStageEdges ? 2 * G * 64 : 1];  // EB[(e*G + k)*64 + row] = row word, end tile e
     uint32_t EC[kStageEdges ? 2 * G * 64 : 1];  // EC[(e*G + k)*64 + col] = column word, end tile e
-    // Q of the row being closed (double-buffered); 16-bit in the lean form,
-    // where the closure runs on packed pairs
-    using QCell = typename std::conditional<kLean, int16_t, int32_t>::type;
+    // Q of the row being closed (double-buffered).  16-bit where every
+    // column of the tile is a cell (T = 64): the closure then runs on packed
+    // pairs.  With fewer posts the padding columns' values are not bounded
+    // by a cell, so those q keep 32-bit values.
+    static constexpr bool kPacked = tile_size(Q) == 64;
+    using QCell = typename std::conditional<kPacked, int16_t, int32_t>::type;
     alignas(16) QCell Qs[2][64];
     int32_t hrow[64];
     alignas(16) int32_t hcT[64];  // hcT[8g + b] = halo partner of column 0 in row 8b + g
@@ -748,22 +751,20 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     // ---- rows bottom-up.  Rows >= T (only when T < 64) are inert: their
     // pushes are -inf in Lp and their pairing into row T-1 is skipped.
     if (g == 7) Qs[1][j] = (QCell)acc[7];  // row 63: Q complete (no row below)
-    // Lean form: U as pairs of 16-bit values for the packed closure, with
-    // -2^15 for minus infinity.  Every real sum Q(i, j') + U(j', j) is at
-    // most X(i, j) < 2^15 and Q >= 0, so no sum leaves the 16-bit range.
-    // u0p is U(8g, j) for the pairing term, -2^15 also where g = 0 (that
-    // lane's term then stays <= 0, which no cell is below; the default form
-    // uses -inf there).
+    // U as pairs of 16-bit values for the packed closure, with -2^15 for
+    // minus infinity.  Every real sum Q(i, j') + U(j', j) is at most
+    // X(i, j) < 2^15 and Q >= 0, so no sum leaves the 16-bit range.  u0p is
+    // U(8g, j) for the pairing term, minus infinity also where g = 0 (that
+    // lane's term then stays <= 0, which no cell is below, and needs no
+    // select per row).
+    constexpr bool kPacked = Lds::kPacked;
     uint32_t up[4] = {0u, 0u, 0u, 0u};
-    int u0p;
-    if constexpr (kLean) {
+    if constexpr (kPacked) {
         auto h16 = [](int v) { return (uint32_t)(v < 0 ? 0x8000 : v); };
 #pragma unroll
         for (int t = 0; t < 4; ++t) up[t] = h16(ureg[2 * t]) | (h16(ureg[2 * t + 1]) << 16);
-        u0p = (g > 0 && ureg[0] >= 0) ? ureg[0] : -32768;
-    } else {
-        u0p = g > 0 ? ureg[0] : kNeg;  // (the pairing term then needs no select per row)
     }
+    const int u0p = (g > 0 && ureg[0] >= 0) ? ureg[0] : (kPacked ? -32768 : kNeg);
     const int xlc = g > 0 ? 8 * g - 1 : 0;
     // end-tile row and column words of the share of row (bb, r): groups
     // x = r + 8m of block bb-1, loaded one row step ahead of their use
@@ -793,9 +794,9 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             // Q(i, 8g..8g+7), the pairing partner of column 8g, L(., i) for
             // the pushes, and the end-tile words of this row's share of
             // block blk-1
-            const int4 qa = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g]);
-            int4 qb = make_int4(0, 0, 0, 0);  // (the lean form's 8 values are all in qa)
-            if constexpr (!kLean) qb = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g + 4]);
+            const int4 qa = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g]);  // 8 values (packed) or 4
+            int4 qb = make_int4(0, 0, 0, 0);
+            if constexpr (!kPacked) qb = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g + 4]);
             int xl = kNeg;
             // X(i+1, 8g-1); lanes of slice 0 read the finished X(i+1, 0)
             // instead, so that their pairing term stays finite and, with
@@ -859,13 +860,14 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             // (X(i, j) >= 0, so 0 stands for no candidate)
             int pt = 0;
             if (i < T - 1) pt = (int)((gmask >> i) & 1u) + xl + u0p;
-            // closure over j' in [8g, 8g+8), then across the 8 lane groups.
-            // Default form: a tree of 3-input maxima (the chain after the Q
-            // read: an add and two levels).  Lean form, where the finish is
-            // bound by instruction issue rather than by its chain: packed
-            // 16-bit adds and maxima over the pairs, then the two halves.
+            // closure over j' in [8g, 8g+8), then across the 8 lane groups:
+            // packed 16-bit adds and maxima over the pairs, then the two
+            // halves and the pairing candidate (the row step is bound by
+            // instruction issue on its SIMD as much as by its chain, so
+            // fewer instructions win here over a shallower 32-bit tree)
+            // (with 32-bit values, a tree of 3-input maxima)
             int xc;
-            if constexpr (kLean) {
+            if constexpr (kPacked) {
                 typedef short s16x2 __attribute__((ext_vector_type(2)));
                 const s16x2 a0 = __builtin_bit_cast(s16x2, qa.x) + __builtin_bit_cast(s16x2, up[0]);
                 const s16x2 a1 = __builtin_bit_cast(s16x2, qa.y) + __builtin_bit_cast(s16x2, up[1]);
