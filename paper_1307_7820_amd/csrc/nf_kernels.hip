@@ -458,7 +458,12 @@ struct TileLds {
     // by a cell, so those q keep 32-bit values.
     static constexpr bool kPacked = tile_size(Q) == 64;
     using QCell = typename std::conditional<kPacked, int16_t, int32_t>::type;
-    alignas(16) QCell Qs[2][64];
+    // The default form gives each of the 8 lane groups a slot, so that every
+    // lane writes its candidate and the row's chain has no masked write (the
+    // readers take the slot of the row's group); the lean form, short of
+    // LDS, keeps one slot written by the row's lanes.
+    static constexpr int kQSlots = kLean ? 1 : 8;
+    alignas(16) QCell Qs[2][kQSlots][64];
     int32_t hrow[64];
     alignas(16) int32_t hcT[64];  // hcT[8g + b] = halo partner of column 0 in row 8b + g
     alignas(16) uint8_t caT[64];  // caT[8g + b] = S_{a+1} of row 8b + g
@@ -495,7 +500,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     uint32_t* EB = s.EB;
     uint32_t* EC = s.EC;
     using QCell = typename Lds::QCell;
-    QCell (*Qs)[64] = s.Qs;
+    QCell (*Qs)[Lds::kQSlots][64] = s.Qs;
     int32_t* hrow = s.hrow;
     int32_t* hcT = s.hcT;
     uint8_t* caT = s.caT;
@@ -739,6 +744,12 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
         const int halo = (i == T - 1) ? hrj : hci[b];  // the last row's partner first, then column 0's
         if (i < T && j < T && (i == T - 1 || j == 0)) acc[b] = max(acc[b], bp + halo);
     }
+    // the pairing bias of row 8b + g at column j for its Q: the bit, or
+    // -inf where the partner X(i, j-1) is in another wavefront (c = 0: the
+    // readers add that term)
+    int pbv[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) pbv[b] = c > 0 ? (int)((pmask >> b) & 1u) : kNeg;
 
     // outputs: dense cells, row words, column words, written after the row
     // loop (global address space: generic
@@ -750,7 +761,9 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
 
     // ---- rows bottom-up.  Rows >= T (only when T < 64) are inert: their
     // pushes are -inf in Lp and their pairing into row T-1 is skipped.
-    if (g == 7) Qs[1][j] = (QCell)acc[7];  // row 63: Q complete (no row below)
+    // row 63: Q complete (no row below)
+    if constexpr (Lds::kQSlots == 8) Qs[1][g][j] = (QCell)acc[7];
+    else if (g == 7) Qs[1][0][j] = (QCell)acc[7];
     // U as pairs of 16-bit values for the packed closure, with -2^15 for
     // minus infinity.  Every real sum Q(i, j') + U(j', j) is at most
     // X(i, j) < 2^15 and Q >= 0, so no sum leaves the 16-bit range.  u0p is
@@ -794,9 +807,10 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             // Q(i, 8g..8g+7), the pairing partner of column 8g, L(., i) for
             // the pushes, and the end-tile words of this row's share of
             // block blk-1
-            const int4 qa = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g]);  // 8 values (packed) or 4
+            const int qslot = Lds::kQSlots == 8 ? (i & 7) : 0;  // (a constant once unrolled)
+            const int4 qa = *reinterpret_cast<const int4*>(&Qs[i & 1][qslot][8 * g]);  // 8 values (packed) or 4
             int4 qb = make_int4(0, 0, 0, 0);
-            if constexpr (!kPacked) qb = *reinterpret_cast<const int4*>(&Qs[i & 1][8 * g + 4]);
+            if constexpr (!kPacked) qb = *reinterpret_cast<const int4*>(&Qs[i & 1][qslot][8 * g + 4]);
             int xl = kNeg;
             // X(i+1, 8g-1); lanes of slice 0 read the finished X(i+1, 0)
             // instead, so that their pairing term stays finite and, with
@@ -830,8 +844,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             // pairing of (i-1, j) with partner X(i, j-1), for the next row's
             // Q: its bit, or -inf where there is no partner (formed here,
             // off the chain)
-            int pb = (i >= 1 && i < T && c > 0) ? (int)((pmask >> ((i - 1) >> 3)) & 1u) : kNeg;
-            __asm__ volatile("" : "+v"(pb));  // kept here, not sunk into the write below
+            const int pb = (i >= 1 && i < T) ? pbv[(i - 1) >> 3] : kNeg;
             __builtin_amdgcn_sched_barrier(0);
             // the end-tile terms of this row's share into the rows of block
             // blk-1 (Eq. 3; the term's value in the low 16 bits, see rterm)
@@ -932,9 +945,19 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                 // they read does not matter (lanes 0, 16, 32, 48 read 0)
                 const int left = __builtin_amdgcn_mov_dpp(xi, 0x111, 0xF, 0xF, true);
                 const int go = (i - 1) & 7, bo = (i - 1) >> 3;
-                if (g == go) Qs[(i - 1) & 1][j] = (QCell)max(acc[bo], left + pb);
+                if constexpr (Lds::kQSlots == 8) {
+                    Qs[(i - 1) & 1][g][j] = (QCell)max(acc[bo], left + pb);  // slot go is row i-1's
+                } else {
+                    if (g == go) Qs[(i - 1) & 1][0][j] = (QCell)max(acc[bo], left + pb);
+                }
             }
-            if (g == 0) Xs[i * 64 + j] = (Cell)xi;
+            // (the 8 lanes of a column hold the same X; in the default form
+            // all of them store it, so that the store is not masked)
+            if constexpr (kLean) {
+                if (g == 0) Xs[i * 64 + j] = (Cell)xi;
+            } else {
+                Xs[i * 64 + j] = (Cell)xi;
+            }
             if (!kLean && rr > 0) edge_terms();
             if constexpr (kStageEdges) {
 #pragma unroll
