@@ -445,10 +445,12 @@ struct TileLds {
     using Cell = typename std::conditional<kLean, int16_t, int32_t>::type;
     Cell Xs[64 * 64];  // finished cells, row-major (values < 2^15)
     // Lp[i*kLS + 8g + b] = L(8b+g, i) for 8b+g < i < T, else -inf; the row
-    // stride kLS = 68 keeps 16-byte rows and spreads the transposed writes
-    // over the banks
-    static constexpr int kLS = 68;
-    int32_t Lp[64 * kLS];
+    // stride keeps 16-byte rows and spreads the transposed writes over the
+    // banks.  The lean form keeps 16-bit values (-2^15 for -inf: a push of
+    // it stays below every cell) to make room for its Q slots.
+    using LCell = typename std::conditional<kLean, int16_t, int32_t>::type;
+    static constexpr int kLS = kLean ? 72 : 68;
+    LCell Lp[64 * kLS];
     uint32_t LW[kBlockFR ? G * 64 : 4];  // LW[k*64 + 8g + b]: row word of row 8b+g, group k, tile (A, A)
     uint32_t EB[kStageEdges ? 2 * G * 64 : 1];  // EB[(e*G + k)*64 + row] = row word, end tile e
     uint32_t EC[kStageEdges ? 2 * G * 64 : 1];  // EC[(e*G + k)*64 + col] = column word, end tile e
@@ -458,12 +460,13 @@ struct TileLds {
     // by a cell, so those q keep 32-bit values.
     static constexpr bool kPacked = tile_size(Q) == 64;
     using QCell = typename std::conditional<kPacked, int16_t, int32_t>::type;
-    // The default form gives each of the 8 lane groups a slot, so that every
-    // lane writes its candidate and the row's chain has no masked write (the
-    // readers take the slot of the row's group); the lean form, short of
-    // LDS, keeps one slot written by the row's lanes.
-    static constexpr int kQSlots = kLean ? 1 : 8;
-    alignas(16) QCell Qs[2][kQSlots][64];
+    // Each of the 8 lane groups has a slot, so that every lane writes its
+    // candidate and the row's chain has no masked write (the readers take the
+    // slot of the row's group).
+    // (slots 144 or 272 bytes apart: the 8 lanes that write one column's
+    // slots hit 8 different banks, and rows stay 16-byte aligned)
+    static constexpr int kQS = kPacked ? 72 : 68;
+    alignas(16) QCell Qs[2][8][kQS];
     int32_t hrow[64];
     alignas(16) int32_t hcT[64];  // hcT[8g + b] = halo partner of column 0 in row 8b + g
     alignas(16) uint8_t caT[64];  // caT[8g + b] = S_{a+1} of row 8b + g
@@ -495,12 +498,12 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     static_assert(!kStageEdges || NE > 8, "every row's share of the end-tile groups is at least one");
     constexpr int LS = Lds::kLS;
     Cell* Xs = s.Xs;
-    int32_t* Lp = s.Lp;
+    typename Lds::LCell* Lp = s.Lp;
     uint32_t* LW = s.LW;
     uint32_t* EB = s.EB;
     uint32_t* EC = s.EC;
     using QCell = typename Lds::QCell;
-    QCell (*Qs)[Lds::kQSlots][64] = s.Qs;
+    QCell (*Qs)[8][Lds::kQS] = s.Qs;
     int32_t* hrow = s.hrow;
     int32_t* hcT = s.hcT;
     uint8_t* caT = s.caT;
@@ -643,8 +646,15 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     if (tid < T) hrow[tid] = hrv;
     if (tid < 64) hcT[(tid & 7) * 8 + (tid >> 3)] = hcv;  // hcv = 0 for rows >= T
     // this thread holds L(8u + wave, lane), u = 0..7: eight consecutive words
-    *reinterpret_cast<int4*>(&Lp[lane * LS + 8 * wave]) = make_int4(lv[0], lv[1], lv[2], lv[3]);
-    *reinterpret_cast<int4*>(&Lp[lane * LS + 8 * wave + 4]) = make_int4(lv[4], lv[5], lv[6], lv[7]);
+    if constexpr (kLean) {
+        auto h16 = [](int v) { return (uint32_t)(uint16_t)(int16_t)max(v, -32768); };
+        *reinterpret_cast<int4*>(&Lp[lane * LS + 8 * wave]) =
+            make_int4((int)(h16(lv[0]) | (h16(lv[1]) << 16)), (int)(h16(lv[2]) | (h16(lv[3]) << 16)),
+                      (int)(h16(lv[4]) | (h16(lv[5]) << 16)), (int)(h16(lv[6]) | (h16(lv[7]) << 16)));
+    } else {
+        *reinterpret_cast<int4*>(&Lp[lane * LS + 8 * wave]) = make_int4(lv[0], lv[1], lv[2], lv[3]);
+        *reinterpret_cast<int4*>(&Lp[lane * LS + 8 * wave + 4]) = make_int4(lv[4], lv[5], lv[6], lv[7]);
+    }
     if (it.nslot > 0) {  // hand the accumulator back zeroed for its next use
 #pragma unroll
         for (int b = 0; b < 8; ++b) (accb + b * 512)[aoff] = 0;
@@ -762,8 +772,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     // ---- rows bottom-up.  Rows >= T (only when T < 64) are inert: their
     // pushes are -inf in Lp and their pairing into row T-1 is skipped.
     // row 63: Q complete (no row below)
-    if constexpr (Lds::kQSlots == 8) Qs[1][g][j] = (QCell)acc[7];
-    else if (g == 7) Qs[1][0][j] = (QCell)acc[7];
+    Qs[1][g][j] = (QCell)acc[7];  // (slot 7 is row 63's)
     // U as pairs of 16-bit values for the packed closure, with -2^15 for
     // minus infinity.  Every real sum Q(i, j') + U(j', j) is at most
     // X(i, j) < 2^15 and Q >= 0, so no sum leaves the 16-bit range.  u0p is
@@ -807,7 +816,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             // Q(i, 8g..8g+7), the pairing partner of column 8g, L(., i) for
             // the pushes, and the end-tile words of this row's share of
             // block blk-1
-            const int qslot = Lds::kQSlots == 8 ? (i & 7) : 0;  // (a constant once unrolled)
+            const int qslot = i & 7;  // the slot of row i's lane group (a constant once unrolled)
             const int4 qa = *reinterpret_cast<const int4*>(&Qs[i & 1][qslot][8 * g]);  // 8 values (packed) or 4
             int4 qb = make_int4(0, 0, 0, 0);
             if constexpr (!kPacked) qb = *reinterpret_cast<const int4*>(&Qs[i & 1][qslot][8 * g + 4]);
@@ -944,20 +953,14 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                 // row_shr:1.  Lanes with c = 0 take no left partner, so what
                 // they read does not matter (lanes 0, 16, 32, 48 read 0)
                 const int left = __builtin_amdgcn_mov_dpp(xi, 0x111, 0xF, 0xF, true);
-                const int go = (i - 1) & 7, bo = (i - 1) >> 3;
-                if constexpr (Lds::kQSlots == 8) {
-                    Qs[(i - 1) & 1][g][j] = (QCell)max(acc[bo], left + pb);  // slot go is row i-1's
-                } else {
-                    if (g == go) Qs[(i - 1) & 1][0][j] = (QCell)max(acc[bo], left + pb);
-                }
+                const int bo = (i - 1) >> 3;
+                // every lane writes its own row's candidate: slot (i-1) & 7
+                // holds row i-1's
+                Qs[(i - 1) & 1][g][j] = (QCell)max(acc[bo], left + pb);
             }
-            // (the 8 lanes of a column hold the same X; in the default form
-            // all of them store it, so that the store is not masked)
-            if constexpr (kLean) {
-                if (g == 0) Xs[i * 64 + j] = (Cell)xi;
-            } else {
-                Xs[i * 64 + j] = (Cell)xi;
-            }
+            // (the 8 lanes of a column hold the same X; all of them store
+            // it, so that the store is not masked)
+            Xs[i * 64 + j] = (Cell)xi;
             if (!kLean && rr > 0) edge_terms();
             if constexpr (kStageEdges) {
 #pragma unroll
