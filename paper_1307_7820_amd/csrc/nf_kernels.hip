@@ -807,6 +807,7 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
     __syncthreads();
     const unsigned long long gmask = GM[g];
 
+    uint32_t evb = 0;  // see edge_terms
 #pragma unroll
     for (int blk = 7; blk >= 0; --blk) {
 #pragma unroll
@@ -857,10 +858,13 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             __builtin_amdgcn_sched_barrier(0);
             // the end-tile terms of this row's share into the rows of block
             // blk-1 (Eq. 3; the term's value in the low 16 bits, see rterm)
+            // The block's 8 row steps keep their terms in a running 16-bit
+            // maximum (evb), which goes into acc[blk-1] once, at the block's
+            // last row: nothing reads acc[blk-1] before that.
             auto edge_terms = [&] {
                 if constexpr (kStageEdges) {
                     if (blk >= 1) {
-                        uint32_t ev = 0;
+                        uint32_t ev = evb;
 #pragma unroll
                         for (int m = 0; m < kEPer; m += 2) {
                             const int m1 = m + 1 < kEPer ? m + 1 : m;
@@ -870,9 +874,10 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
                             const uint32_t t1 = (m + 1 < kEPer && x1 < NE)
                                                     ? erw[m1] + (kLean ? erc[m1] : col_word(x1)) + rg[m1]
                                                     : t0;
-                            ev = max3_u16(m == 0 ? t0 : ev, t0, t1);
+                            ev = max3_u16((m == 0 && rr == 7) ? t0 : ev, t0, t1);  // rr = 7: the block's first row
                         }
-                        acc[blk - 1] = max_lo16(acc[blk - 1], ev);
+                        if (rr == 0) acc[blk - 1] = max_lo16(acc[blk - 1], ev);
+                        else evb = ev;
                     }
                 }
             };
