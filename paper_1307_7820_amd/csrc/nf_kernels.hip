@@ -921,9 +921,9 @@ __device__ __forceinline__ void tile_body(const TileWork& it, uint8_t* Rl, const
             }
             // the last row of a block: the next row (in block blk-1) takes
             // its Q from acc[blk-1] now, so its end-tile terms go in first.
-            // The lean form sums them here at every row, in the same block
-            // of code as their gathers (after the writes below, the loaded
-            // bytes would need masking again)
+            // The lean form sums them here at every row: it is bound by
+            // instruction issue, not by the row's chain, which the default
+            // form keeps them off by summing after the writes below
             if (kLean || rr == 0) edge_terms();
             if constexpr (kBlockFR) {
                 if (rr == 0 && blk >= 1) {
